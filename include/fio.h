@@ -1,0 +1,185 @@
+/*
+ * fio.h -- C ABI of the MI355X butterfly evaluator for 2-D discrete Fourier
+ * integral operators (Candes, Demanet & Ying, "A fast butterfly algorithm
+ * for the computation of Fourier integral operators").
+ *
+ * The operator (eq:dfio, Sec. 1):
+ *
+ *     u(x) = sum_{k in Omega} exp(2 pi i Phi(x,k)) f(k),   x in X,
+ *     X     = {(i1/N, i2/N) : 0 <= i1,i2 < N},
+ *     Omega = {(k1,k2)      : -N/2 <= k1,k2 < N/2},
+ *
+ * is approximated by the butterfly of Sec. 4: the sources are mapped to
+ * polar coordinates p (eq:polar), the quadtrees T_X and T_P are paired level
+ * by level with l(A) + l(B) = L = log2 N, and per box pair (A,B) a q x q
+ * tensor Chebyshev expansion delta^{AB}_t is carried from the leaves of T_P
+ * (initialisation, eq:alg2a) through the p-interpolation levels (eq:alg2b),
+ * the switch (eq:alg2m) and the x-interpolation levels (eq:alg2c) to the
+ * potentials (termination, eq:alg2d).  As in the numerical section, the
+ * recursion starts s levels above the leaves of T_P and stops s levels
+ * below its root (pairs (A at level s, B at level L-s) first, (A at level
+ * L-s, B at level s) last, the potentials summing over the 4^s boxes B).
+ *
+ * All compute runs in HIP kernels on the current device.  Every pointer
+ * marked "device" must be device memory on that device; the library never
+ * reads or writes host copies of the data.  Calls are asynchronous on the
+ * given stream (a hipStream_t passed as void*, NULL = the null stream).
+ *
+ * Error behaviour: every function returns FIO_OK (0) or a negative code;
+ * argument errors are detected before any launch.  fio_last_error() gives a
+ * human-readable message for the calling thread's last failure.
+ *
+ * Thread-safety: distinct plans may be used concurrently; one plan owns one
+ * workspace, so concurrent applies on the same plan must be serialised by
+ * the caller (e.g. by issuing them on one stream).
+ */
+#ifndef FIO_H
+#define FIO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define FIO_OK        0
+#define FIO_EINVAL   (-1)  /* bad argument (N, q, s, lm, nrhs, pointer, ...) */
+#define FIO_ENOMEM   (-2)  /* device or host allocation failed               */
+#define FIO_EDEVICE  (-3)  /* a HIP runtime call or kernel launch failed     */
+
+/* ---- phase functions ----------------------------------------------------
+ * Phi must be smooth for k != 0 and homogeneous of degree 1 in k (Sec. 1).
+ *
+ * FIO_PHASE_FOURIER:  Phi(x,k) = x . k   (the 2-D DFT; the closed-form check)
+ * FIO_PHASE_ELLIPSE:  Phi(x,k) = x . k + sqrt(c1(x)^2 k1^2 + c2(x)^2 k2^2),
+ *     c1(x) = a1 (2 + (1+eta1) sin(2 pi x1) sin(2 pi x2)) / 3,
+ *     c2(x) = a2 (2 + (1+eta2) cos(2 pi x1) cos(2 pi x2)) / 3,
+ *   which is eq:ex1 (Sec. 5) for a1 = a2 = 1, eta1 = eta2 = 0.  a1, a2 are
+ *   velocity scalings (e.g. learnable), eta1, eta2 perturb the modulation.
+ *   Requires a1, a2 > 0 and -1 <= eta1, eta2 <= 1 (so c_j > 0).         */
+#define FIO_PHASE_FOURIER 0
+#define FIO_PHASE_ELLIPSE 1
+
+typedef struct {
+    int    kind;       /* FIO_PHASE_*                     */
+    double a1, a2;     /* ELLIPSE velocity scalings (> 0) */
+    double eta1, eta2; /* ELLIPSE modulation amplitudes   */
+} fio_phase_t;
+
+/* ---- precision ----------------------------------------------------------
+ * Phases Phi are always evaluated in FP64 and reduced mod 1 in FP64 (their
+ * magnitude reaches ~N cycles, so single precision would lose the phase).
+ *
+ * FIO_C128: f, u are complex128; weights, exponentials and contractions FP64.
+ * FIO_C64:  f, u are complex64; the reduced phase feeds an FP32 exponential,
+ *           weights and interpolation contractions are FP32.              */
+#define FIO_C128 0
+#define FIO_C64  1
+
+typedef struct fio_plan_s *fio_plan_t;
+
+/* Options for fio_plan_ex.  Any field set to -1 takes its default. */
+typedef struct {
+    int s;        /* levels skipped at each end of the trees; default min(3, L/2)
+                     (the numerical section starts at level log2N-3 of T_P and
+                     stops at level 3); s = 0 is Sec. 4 verbatim               */
+    int lm;       /* switch level (eq:alg2m); default floor(L/2); must satisfy
+                     s <= lm <= L - s                                          */
+    int dtype;    /* FIO_C64 (default) or FIO_C128                             */
+    int nrhs_max; /* reserved: the largest nrhs a batched apply will use
+                     (default 1); the plain path needs no per-RHS workspace    */
+} fio_plan_opts_t;
+
+/* Geometry and sizes of a plan. */
+typedef struct {
+    int N, q, L, s, lm, dtype;
+    int64_t n_pairs;          /* box pairs per level = N^2                        */
+    int64_t weights_per_level;/* complex weights per level per RHS = N^2 q^2      */
+    int64_t workspace_bytes;  /* device memory owned by the plan                  */
+    int max_box_sources;      /* largest number of sources in a level-(L-s) box */
+} fio_plan_info_t;
+
+/* Create a plan for an N x N problem with q Chebyshev points per dimension
+ * (r = q^2 expansion terms per box pair, Sec. 3).
+ *   N:     power of two, 8 <= N <= 8192 (N = 2^L).
+ *   q:     3 <= q <= 16.
+ *   phase: host pointer, copied into the plan.
+ *   out:   host pointer receiving the plan handle.
+ * Builds T_P for the polar images of Omega (Sec. 4 step 1; sources sorted by
+ * their level-(L-s) box) and the interpolation tables (the Lagrange values
+ * L^B_t(p^{B_c}_t') are the same for every pair and level, Sec. 4), and
+ * allocates two weight buffers of N^2 q^2 complex values each (only two
+ * consecutive levels of weights are ever live, Sec. 4) on the current
+ * device.  Returns FIO_OK, FIO_EINVAL, FIO_ENOMEM or FIO_EDEVICE. */
+int fio_plan(int N, int q, const fio_phase_t *phase, fio_plan_t *out);
+int fio_plan_ex(int N, int q, const fio_phase_t *phase,
+                const fio_plan_opts_t *opts, fio_plan_t *out);
+
+/* Replace the phase parameters of a plan (e.g. after a gradient step on
+ * a1, a2).  The trees and tables do not depend on the phase. */
+int fio_set_phase(fio_plan_t plan, const fio_phase_t *phase);
+
+int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info);
+
+/* Forward butterfly u = B f (approximates eq:dfio).
+ *   f: device, nrhs x N x N complex (plan dtype), f[r][k1+N/2][k2+N/2].
+ *      Read only.
+ *   u: device, nrhs x N x N complex (plan dtype), u[r][i1][i2] = u_r(i1/N,
+ *      i2/N).  Fully overwritten.  Must not overlap f.
+ *   nrhs >= 1 right-hand sides, processed one after another.
+ * Asynchronous on `stream`; FIO_EINVAL before any launch on bad arguments. */
+int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream);
+
+/* Adjoint butterfly f = B^H u: the exact conjugate transpose of the
+ * forward pipeline (termination^H, x-levels^H, switch^H, p-levels^H,
+ * initialisation^H), which approximates f(k) = sum_x exp(-2 pi i Phi(x,k))
+ * u(x).  Same layouts and rules as fio_apply with the roles of f, u swapped. */
+int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, void *stream);
+
+/* Diagnostics: run the forward pipeline for one right-hand side up to and
+ * including stage `stage` and copy that stage's weights to `weights`.
+ *   stage 0                 : initialisation, level s
+ *   stage 1 .. lm-s         : p-level s+stage
+ *   stage lm-s+1            : after the switch, level lm
+ *   stage lm-s+1+j (j >= 1) : x-level lm+j, up to level L-s
+ *   weights: device, N^2 q^2 complex (plan dtype), laid out as
+ *     weights[(mA * 4^(L-l) + mB) * q^2 + t1*q + t2]
+ *   with l the stage's level, mA the Morton index of A at level l of T_X
+ *   (bits of the x1 box index at odd positions, of the x2 index at even
+ *   positions), mB the Morton index of B at level L-l of T_P (p1 bits odd,
+ *   p2 bits even), and (t1, t2) the Chebyshev node of z_t1 in the first and
+ *   z_t2 in the second coordinate. */
+int fio_debug_stage(fio_plan_t plan, const void *f, int stage, void *weights, void *stream);
+
+/* ---- per-kernel timing ----------------------------------------------------
+ * With profiling enabled, every kernel launch of the plan is bracketed by
+ * two HIP events recorded on the launch stream.  fio_profile_read waits for
+ * those events, writes per kernel kind the summed elapsed milliseconds and
+ * the number of launches since the last read (arrays of length n, n <= 
+ * FIO_KERNEL_KINDS, host memory), and resets the counters.               */
+#define FIO_K_INIT        0
+#define FIO_K_PLEVEL      1
+#define FIO_K_SWITCH      2
+#define FIO_K_XLEVEL      3
+#define FIO_K_TERM        4
+#define FIO_K_TERM_ADJ    5
+#define FIO_K_XLEVEL_ADJ  6
+#define FIO_K_SWITCH_ADJ  7
+#define FIO_K_PLEVEL_ADJ  8
+#define FIO_K_INIT_ADJ    9
+#define FIO_KERNEL_KINDS 10
+
+int fio_profile_enable(fio_plan_t plan, int enable);
+int fio_profile_read(fio_plan_t plan, double *ms, int64_t *launches, int n);
+
+/* Free the plan and its device workspace (synchronises the device first). */
+int fio_destroy(fio_plan_t plan);
+
+/* Message describing the calling thread's last error ("" if none). */
+const char *fio_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIO_H */

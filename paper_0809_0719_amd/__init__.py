@@ -1,0 +1,253 @@
+"""MI355X butterfly evaluator for 2-D discrete Fourier integral operators.
+
+    u(x) = sum_{k in Omega} exp(2 pi i Phi(x,k)) f(k),  x in X          (eq:dfio)
+
+evaluated by the butterfly algorithm of Candes, Demanet & Ying (Sec. 4):
+polar P-tree x dyadic X-tree, tensor Chebyshev expansions per box pair,
+HIP kernels for gfx950 behind the C ABI of ``include/fio.h``.
+
+This module is argument marshalling only: every step of the pass runs in
+the HIP library ``libfio.so``.  PyTorch provides device memory and streams.
+If the library is missing the calls raise; there is no CPU fallback.
+
+    >>> plan = Plan(1024, 9)                       # eq:ex1 phase, FP32 weights
+    >>> u = plan.apply(f)                          # f: (N, N) or (R, N, N) complex64 on cuda
+    >>> g = plan.adjoint(u)                        # B^H u
+    >>> u = fio_apply(f, plan)                     # autograd: backward is the adjoint
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = [
+    "Phase", "Plan", "FIOApply", "fio_apply", "load_library", "library_path",
+    "FOURIER", "ELLIPSE", "C128", "C64", "EXPORTED_SYMBOLS",
+]
+
+FOURIER = 0
+ELLIPSE = 1
+C128 = 0
+C64 = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfio.so")
+
+# every symbol include/fio.h declares
+EXPORTED_SYMBOLS = (
+    "fio_plan", "fio_plan_ex", "fio_set_phase", "fio_plan_get_info", "fio_apply",
+    "fio_apply_adjoint", "fio_debug_stage", "fio_destroy", "fio_last_error",
+    "fio_profile_enable", "fio_profile_read",
+)
+
+# kernel kinds of fio_profile_read (FIO_K_* in include/fio.h)
+KERNEL_KINDS = ("init", "plevel", "switch", "xlevel", "term",
+                "term_adj", "xlevel_adj", "switch_adj", "plevel_adj", "init_adj")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+@dataclass(frozen=True)
+class Phase:
+    """Phase descriptor (``fio_phase_t``).  ELLIPSE with the defaults is eq:ex1."""
+
+    kind: int = ELLIPSE
+    a1: float = 1.0
+    a2: float = 1.0
+    eta1: float = 0.0
+    eta2: float = 0.0
+
+
+class _CPhase(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("a1", ctypes.c_double), ("a2", ctypes.c_double),
+                ("eta1", ctypes.c_double), ("eta2", ctypes.c_double)]
+
+
+class _COpts(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int), ("lm", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("nrhs_max", ctypes.c_int)]
+
+
+class _CInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("q", ctypes.c_int), ("L", ctypes.c_int), ("s", ctypes.c_int),
+                ("lm", ctypes.c_int), ("dtype", ctypes.c_int), ("n_pairs", ctypes.c_int64),
+                ("weights_per_level", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("max_box_sources", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load ``libfio.so`` (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"HIP library {_LIB_PATH} is not built; run "
+                           "`python -m paper_0809_0719_amd.build` (or __graft_entry__.build())")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i = ctypes.c_void_p, ctypes.c_int
+    lib.fio_plan.argtypes = [i, i, ctypes.POINTER(_CPhase), ctypes.POINTER(vp)]
+    lib.fio_plan_ex.argtypes = [i, i, ctypes.POINTER(_CPhase), ctypes.POINTER(_COpts), ctypes.POINTER(vp)]
+    lib.fio_set_phase.argtypes = [vp, ctypes.POINTER(_CPhase)]
+    lib.fio_plan_get_info.argtypes = [vp, ctypes.POINTER(_CInfo)]
+    lib.fio_apply.argtypes = [vp, vp, vp, i, vp]
+    lib.fio_apply_adjoint.argtypes = [vp, vp, vp, i, vp]
+    lib.fio_debug_stage.argtypes = [vp, vp, i, vp, vp]
+    lib.fio_destroy.argtypes = [vp]
+    lib.fio_profile_enable.argtypes = [vp, i]
+    lib.fio_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i]
+    lib.fio_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED_SYMBOLS:
+        if name != "fio_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = load_library().fio_last_error().decode(errors="replace")
+        raise RuntimeError(f"{what} failed ({rc}): {msg}")
+
+
+def _cphase(ph: Phase) -> _CPhase:
+    return _CPhase(int(ph.kind), float(ph.a1), float(ph.a2), float(ph.eta1), float(ph.eta2))
+
+
+class Plan:
+    """A butterfly plan (``fio_plan_ex``) on the current HIP device.
+
+    N: grid side (power of two, 8..8192); q: Chebyshev points per dimension
+    (3..16); phase: :class:`Phase`; s, lm: start offset and switch level
+    (defaults min(3, L/2) and L/2); dtype: torch.complex64 (FP32 weights,
+    FP64 phases) or torch.complex128 (FP64 throughout).
+    """
+
+    def __init__(self, N: int, q: int, phase: Phase = Phase(), s: int | None = None,
+                 lm: int | None = None, dtype: torch.dtype = torch.complex64):
+        lib = load_library()
+        if dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        self.dtype = dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        opts = _COpts(-1 if s is None else int(s), -1 if lm is None else int(lm),
+                      C64 if dtype == torch.complex64 else C128, -1)
+        h = ctypes.c_void_p()
+        _check(lib.fio_plan_ex(int(N), int(q), ctypes.byref(_cphase(phase)), ctypes.byref(opts),
+                               ctypes.byref(h)), "fio_plan_ex")
+        self._h = h
+        self.phase = phase
+        info = _CInfo()
+        _check(lib.fio_plan_get_info(h, ctypes.byref(info)), "fio_plan_get_info")
+        self.N, self.q, self.L, self.s, self.lm = info.N, info.q, info.L, info.s, info.lm
+        self.workspace_bytes = int(info.workspace_bytes)
+        self.max_box_sources = int(info.max_box_sources)
+        self.n_stages = self.L - 2 * self.s + 2
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().fio_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- parameters ---------------------------------------------------------
+    def set_phase(self, phase: Phase):
+        _check(load_library().fio_set_phase(self._h, ctypes.byref(_cphase(phase))), "fio_set_phase")
+        self.phase = phase
+
+    # -- helpers ------------------------------------------------------------
+    def _prep(self, x: torch.Tensor, name: str):
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if x.dtype != self.dtype:
+            raise TypeError(f"{name} must be {self.dtype} (got {x.dtype})")
+        if x.shape[-2:] != (self.N, self.N):
+            raise ValueError(f"{name} must have trailing shape ({self.N}, {self.N}), got {tuple(x.shape)}")
+        if x.device != self.device:
+            raise ValueError(f"{name} is on {x.device}, plan on {self.device}")
+        x = x.contiguous()
+        nrhs = x.numel() // (self.N * self.N)
+        return x, nrhs
+
+    # -- the butterfly ------------------------------------------------------
+    def apply(self, f: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """u = B f for f of shape (..., N, N) with f[..., k1+N/2, k2+N/2]."""
+        f, nrhs = self._prep(f, "f")
+        u = torch.empty_like(f) if out is None else out
+        if nrhs == 0:
+            return u
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().fio_apply(self._h, f.data_ptr(), u.data_ptr(), nrhs, st), "fio_apply")
+        return u
+
+    def adjoint(self, u: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """f = B^H u for u of shape (..., N, N) with u[..., i1, i2] = u(i1/N, i2/N)."""
+        u, nrhs = self._prep(u, "u")
+        f = torch.empty_like(u) if out is None else out
+        if nrhs == 0:
+            return f
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().fio_apply_adjoint(self._h, u.data_ptr(), f.data_ptr(), nrhs, st),
+               "fio_apply_adjoint")
+        return f
+
+    def debug_stage(self, f: torch.Tensor, stage: int) -> torch.Tensor:
+        """Weights after forward stage ``stage`` (layout in include/fio.h)."""
+        f, nrhs = self._prep(f, "f")
+        if nrhs != 1:
+            raise ValueError("debug_stage takes one right-hand side")
+        w = torch.empty(self.N * self.N * self.q * self.q, dtype=self.dtype, device=self.device)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().fio_debug_stage(self._h, f.data_ptr(), int(stage), w.data_ptr(), st),
+               "fio_debug_stage")
+        return w
+
+    # -- per-kernel timing ----------------------------------------------------
+    def profile(self, enable: bool = True):
+        """Bracket every kernel launch with HIP events on its stream."""
+        _check(load_library().fio_profile_enable(self._h, int(bool(enable))), "fio_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{kind: (total ms, launches)} since the last read (waits for the events)."""
+        n = len(KERNEL_KINDS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(load_library().fio_profile_read(self._h, ms, cnt, n), "fio_profile_read")
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(KERNEL_KINDS) if cnt[i]}
+
+    def stage_level(self, stage: int) -> int:
+        """Tree level l of T_X of the weights after ``stage``."""
+        if stage <= self.lm - self.s:
+            return self.s + stage
+        return self.lm + (stage - (self.lm - self.s) - 1)
+
+
+class FIOApply(torch.autograd.Function):
+    """u = B f with backward grad_f = B^H grad_u (B is C-linear, so the
+    conjugate-Wirtinger vector-Jacobian product is the adjoint)."""
+
+    @staticmethod
+    def forward(ctx, f: torch.Tensor, plan: Plan):
+        ctx.plan = plan
+        return plan.apply(f)
+
+    @staticmethod
+    def backward(ctx, grad_u: torch.Tensor):
+        return ctx.plan.adjoint(grad_u.contiguous()), None
+
+
+def fio_apply(f: torch.Tensor, plan: Plan) -> torch.Tensor:
+    return FIOApply.apply(f, plan)

@@ -1,0 +1,78 @@
+// Internal definitions shared by the host plan (fio_plan.cpp) and the HIP
+// kernels (fio_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fio.h"
+
+namespace fio {
+
+constexpr int QMIN = 3;
+constexpr int QMAX = 16;
+
+// Phase parameters as the kernels see them.  For FOURIER the ellipse
+// coefficients are zero, which makes the square-root term vanish exactly.
+struct PhaseDev {
+    int kind;
+    double a1, a2, eta1, eta2;
+};
+
+// Geometry of a plan, passed by value to every kernel.
+struct Geom {
+    int N;       // grid side
+    int L;       // log2 N
+    int q;       // Chebyshev points per dimension
+    int s;       // levels skipped at each end
+    int lm;      // switch level
+    double rho_scale;  // (sqrt(2)/2) N : |k| = rho_scale * p1 (eq:polar)
+};
+
+// Device-resident tables of a plan (all FP64 except where a float copy is kept).
+//   z[q]            Chebyshev nodes cos(i pi/(q-1))/2 (middle node exactly 0 for odd q)
+//   lam[q]          barycentric weights 1/prod_{j!=i}(z_i - z_j)
+//   M[2][q][q]      M_c[t][j] = L_t((z_j + c - 1/2)/2): parent basis t at child node j
+//   Tt[2^s][q]      Tt[j][t] = L_t(j 2^-s - 1/2): basis t at the 2^s grid points of a leaf-level box
+struct Tables {
+    const double *z;
+    const double *lam;
+    const double *M;    // FP64 copy
+    const float  *Mf;   // FP32 copy
+    const double *Tt;
+    const float  *Ttf;
+};
+
+// Sources of T_P sorted by their box at level L-s (a CSR over Morton order).
+struct Sources {
+    const int32_t *idx;     // Omega index (k1+N/2)*N + (k2+N/2) of the j-th sorted source
+    const double2 *p;       // (p1, p2) of the j-th sorted source
+    const int32_t *off;     // off[mB] .. off[mB+1]: sources of the box with Morton index mB
+};
+
+// Kernel launchers (defined in fio_kernels.hip).  All return hipError_t of the launch.
+// `dtype` selects FP64 (FIO_C128) or FP32 (FIO_C64) weights.
+hipError_t launch_init(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
+                       const Sources &src, const void *f, void *w_out, hipStream_t st);
+hipError_t launch_plevel(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
+                         const void *w_in, void *w_out, hipStream_t st);
+hipError_t launch_switch(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
+                         void *w, hipStream_t st);
+hipError_t launch_xlevel(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
+                         const void *w_in, void *w_out, hipStream_t st);
+hipError_t launch_term(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
+                       const void *w_in, void *u, hipStream_t st);
+
+// Adjoint launchers: exact conjugate transposes of the above.
+hipError_t launch_term_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
+                           const void *u, void *w_out, hipStream_t st);
+hipError_t launch_xlevel_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
+                             const void *w_in, void *w_out, hipStream_t st);
+hipError_t launch_switch_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
+                             void *w, hipStream_t st);
+hipError_t launch_plevel_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
+                             const void *w_in, void *w_out, hipStream_t st);
+hipError_t launch_init_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
+                           const Sources &src, const void *w_in, void *f, hipStream_t st);
+
+}  // namespace fio

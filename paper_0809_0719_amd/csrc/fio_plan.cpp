@@ -1,0 +1,541 @@
+// Host side of the C ABI: argument validation, the plan (trees of Sec. 4
+// step 1, interpolation tables, workspace), and the level schedule that
+// drives the kernels of fio_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fio_internal.h"
+
+using namespace fio;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? FIO_ENOMEM : FIO_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ilog2_exact(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return ((1 << l) == n) ? l : -1;
+}
+
+uint32_t morton(uint32_t b1, uint32_t b2) {
+    uint32_t m = 0;
+    for (int i = 0; i < 16; ++i) {
+        m |= ((b2 >> i) & 1u) << (2 * i);
+        m |= ((b1 >> i) & 1u) << (2 * i + 1);
+    }
+    return m;
+}
+
+int validate_phase(const fio_phase_t *ph) {
+    if (!ph) return fail(FIO_EINVAL, "phase is NULL");
+    if (ph->kind != FIO_PHASE_FOURIER && ph->kind != FIO_PHASE_ELLIPSE)
+        return fail(FIO_EINVAL, "unknown phase kind %d", ph->kind);
+    if (ph->kind == FIO_PHASE_ELLIPSE) {
+        if (!(ph->a1 > 0.0) || !(ph->a2 > 0.0) || !std::isfinite(ph->a1) || !std::isfinite(ph->a2))
+            return fail(FIO_EINVAL, "ellipse phase needs a1, a2 > 0 (got %g, %g)", ph->a1, ph->a2);
+        if (!(ph->eta1 >= -1.0 && ph->eta1 <= 1.0) || !(ph->eta2 >= -1.0 && ph->eta2 <= 1.0))
+            return fail(FIO_EINVAL, "ellipse phase needs -1 <= eta1, eta2 <= 1 (got %g, %g)", ph->eta1, ph->eta2);
+    }
+    return FIO_OK;
+}
+
+PhaseDev to_dev(const fio_phase_t *ph) {
+    PhaseDev d;
+    d.kind = ph->kind;
+    d.a1 = ph->a1;
+    d.a2 = ph->a2;
+    d.eta1 = ph->eta1;
+    d.eta2 = ph->eta2;
+    return d;
+}
+
+// Lagrange basis L_t(u) on nodes z (product form), for the host tables.
+double lagrange(const std::vector<double> &z, int t, double u) {
+    double v = 1.0;
+    for (size_t j = 0; j < z.size(); ++j)
+        if ((int)j != t) v *= (u - z[j]) / (z[t] - z[j]);
+    return v;
+}
+
+}  // namespace
+
+struct fio_plan_s {
+    int N = 0, q = 0, L = 0, s = 0, lm = 0, dtype = FIO_C64, device = 0;
+    fio_phase_t phase{};
+    int max_box = 0;
+    size_t wbytes = 0;       // bytes of one weight buffer
+    size_t total_bytes = 0;  // all device memory of the plan
+    void *w0 = nullptr, *w1 = nullptr;
+    void *dtab = nullptr;    // tables
+    int32_t *d_idx = nullptr, *d_off = nullptr;
+    double2 *d_p = nullptr;
+    Tables tb{};
+    Geom geom{};
+    // profiling: event pairs recorded around each launch
+    bool prof = false;
+    std::vector<hipEvent_t> ev;      // 2 per recorded launch
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+};
+
+namespace {
+
+void free_plan(fio_plan_s *p) {
+    if (!p) return;
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    (void)hipFree(p->w0);
+    (void)hipFree(p->w1);
+    (void)hipFree(p->dtab);
+    (void)hipFree(p->d_idx);
+    (void)hipFree(p->d_off);
+    (void)hipFree(p->d_p);
+    delete p;
+}
+
+int dmalloc(void **ptr, size_t bytes, size_t *total, const char *what) {
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return hip_fail(e, what);
+    }
+    *total += bytes;
+    return FIO_OK;
+}
+
+int check_plan(fio_plan_t plan) {
+    if (!plan) return fail(FIO_EINVAL, "plan is NULL");
+    return FIO_OK;
+}
+
+int set_device(fio_plan_t plan) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != plan->device) {
+        e = hipSetDevice(plan->device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    }
+    return FIO_OK;
+}
+
+// Bracket one launch with events when profiling is on.
+struct Timed {
+    fio_plan_s *p;
+    int kind;
+    hipStream_t st;
+    size_t slot = (size_t)-1;
+    Timed(fio_plan_s *p_, int kind_, hipStream_t st_) : p(p_), kind(kind_), st(st_) {
+        if (!p->prof) return;
+        if (p->ev_used * 2 + 2 > p->ev.size()) {
+            for (int i = 0; i < 64; ++i) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                p->ev.push_back(e);
+            }
+            p->ev_kind.resize(p->ev.size() / 2);
+        }
+        slot = p->ev_used++;
+        p->ev_kind[slot] = kind;
+        (void)hipEventRecord(p->ev[2 * slot], st);
+    }
+    ~Timed() {
+        if (slot != (size_t)-1) (void)hipEventRecord(p->ev[2 * slot + 1], st);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *fio_last_error(void) { return g_last_error.c_str(); }
+
+int fio_plan(int N, int q, const fio_phase_t *phase, fio_plan_t *out) {
+    return fio_plan_ex(N, q, phase, nullptr, out);
+}
+
+int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *opts, fio_plan_t *out) {
+    g_last_error.clear();
+    if (!out) return fail(FIO_EINVAL, "out is NULL");
+    *out = nullptr;
+    const int L = ilog2_exact(N);
+    if (L < 0 || N < 8 || N > 8192) return fail(FIO_EINVAL, "N must be a power of two in [8, 8192] (got %d)", N);
+    if (q < QMIN || q > QMAX) return fail(FIO_EINVAL, "q must be in [%d, %d] (got %d)", QMIN, QMAX, q);
+    int rc = validate_phase(phase);
+    if (rc) return rc;
+    int s = std::min(3, L / 2), lm = L / 2, dtype = FIO_C64;
+    if (opts) {
+        if (opts->s != -1) s = opts->s;
+        if (opts->lm != -1) lm = opts->lm;
+        if (opts->dtype != -1) dtype = opts->dtype;
+        if (opts->nrhs_max != -1 && opts->nrhs_max < 1)
+            return fail(FIO_EINVAL, "nrhs_max must be >= 1 (got %d)", opts->nrhs_max);
+    }
+    if (s < 0 || s > 3) return fail(FIO_EINVAL, "s must be in [0, 3] (got %d)", s);
+    if (!(s <= lm && lm <= L - s)) return fail(FIO_EINVAL, "need s <= lm <= L - s (s=%d, lm=%d, L=%d)", s, lm, L);
+    if (dtype != FIO_C64 && dtype != FIO_C128) return fail(FIO_EINVAL, "unknown dtype %d", dtype);
+
+    fio_plan_s *p = new fio_plan_s();
+    p->N = N;
+    p->q = q;
+    p->L = L;
+    p->s = s;
+    p->lm = lm;
+    p->dtype = dtype;
+    p->phase = *phase;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+
+    // ---- T_P: polar images of Omega (eq:polar), sorted by level-(L-s) box
+    const int lB = L - s;
+    const int nb1 = 1 << lB;
+    const size_t n2 = (size_t)N * N;
+    const size_t nboxes = (size_t)1 << (2 * lB);
+    std::vector<double2> pp(n2);
+    std::vector<uint32_t> boxof(n2);
+    std::vector<int32_t> count(nboxes + 1, 0);
+    const double two_pi = 2.0 * M_PI;
+    for (int j1 = 0; j1 < N; ++j1) {
+        for (int j2 = 0; j2 < N; ++j2) {
+            const double k1 = j1 - N / 2, k2 = j2 - N / 2;
+            double p1 = std::sqrt(2.0 * (k1 * k1 + k2 * k2)) / N;
+            double p2 = std::atan2(k2, k1) / two_pi;
+            if (p2 < 0.0) p2 += 1.0;
+            const size_t idx = (size_t)j1 * N + j2;
+            pp[idx] = make_double2(p1, p2);
+            const int b1 = std::min((int)std::floor(p1 * nb1), nb1 - 1);
+            const int b2 = std::min((int)std::floor(p2 * nb1), nb1 - 1);
+            const uint32_t m = morton((uint32_t)b1, (uint32_t)b2);
+            boxof[idx] = m;
+            count[m + 1]++;
+        }
+    }
+    for (size_t b = 0; b < nboxes; ++b) {
+        p->max_box = std::max(p->max_box, count[b + 1]);
+        count[b + 1] += count[b];
+    }
+    std::vector<int32_t> sidx(n2);
+    std::vector<double2> sp(n2);
+    {
+        std::vector<int32_t> fillp(count.begin(), count.end() - 1);
+        for (size_t idx = 0; idx < n2; ++idx) {  // stable: Omega order within a box
+            const int32_t dst = fillp[boxof[idx]]++;
+            sidx[dst] = (int32_t)idx;
+            sp[dst] = pp[idx];
+        }
+    }
+
+    // ---- tables (Sec. 3 Chebyshev grid; Sec. 4 Kronecker factors)
+    std::vector<double> z(q), lam(q);
+    for (int i = 0; i < q; ++i) z[i] = 0.5 * std::cos(i * M_PI / (q - 1));
+    for (int i = 0; i < q / 2; ++i) z[q - 1 - i] = -z[i];  // exact symmetry z_{q-1-i} = -z_i
+    if (q & 1) z[q / 2] = 0.0;
+    for (int i = 0; i < q; ++i) {
+        double d = 1.0;
+        for (int j = 0; j < q; ++j)
+            if (j != i) d *= (z[i] - z[j]);
+        lam[i] = 1.0 / d;
+    }
+    const int m = 1 << s;
+    std::vector<double> M(2 * q * q), Tt((size_t)m * q);
+    for (int c = 0; c < 2; ++c)
+        for (int t = 0; t < q; ++t)
+            for (int j = 0; j < q; ++j) M[(c * q + t) * q + j] = lagrange(z, t, (z[j] + c - 0.5) / 2.0);
+    for (int jj = 0; jj < m; ++jj)
+        for (int t = 0; t < q; ++t) Tt[jj * q + t] = lagrange(z, t, (double)jj / m - 0.5);
+    std::vector<float> Mf(M.begin(), M.end()), Ttf(Tt.begin(), Tt.end());
+
+    // table blob: z | lam | M | Tt | Mf | Ttf  (256-byte aligned pieces)
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t oz = 0, olam = al(oz + q * 8), oM = al(olam + q * 8), oT = al(oM + M.size() * 8),
+                 oMf = al(oT + Tt.size() * 8), oTf = al(oMf + Mf.size() * 4), tbytes = al(oTf + Ttf.size() * 4);
+    std::vector<unsigned char> blob(tbytes, 0);
+    memcpy(&blob[oz], z.data(), q * 8);
+    memcpy(&blob[olam], lam.data(), q * 8);
+    memcpy(&blob[oM], M.data(), M.size() * 8);
+    memcpy(&blob[oT], Tt.data(), Tt.size() * 8);
+    memcpy(&blob[oMf], Mf.data(), Mf.size() * 4);
+    memcpy(&blob[oTf], Ttf.data(), Ttf.size() * 4);
+
+    // ---- device memory
+    const size_t csize = dtype == FIO_C128 ? 16 : 8;
+    p->wbytes = n2 * (size_t)q * q * csize;
+    size_t tot = 0;
+    if ((rc = dmalloc(&p->w0, p->wbytes, &tot, "weights 0")) || (rc = dmalloc(&p->w1, p->wbytes, &tot, "weights 1")) ||
+        (rc = dmalloc(&p->dtab, tbytes, &tot, "tables")) ||
+        (rc = dmalloc((void **)&p->d_idx, n2 * 4, &tot, "source index")) ||
+        (rc = dmalloc((void **)&p->d_p, n2 * sizeof(double2), &tot, "source p")) ||
+        (rc = dmalloc((void **)&p->d_off, (nboxes + 1) * 4, &tot, "box offsets"))) {
+        free_plan(p);
+        return rc;
+    }
+    p->total_bytes = tot;
+    if ((e = hipMemcpy(p->dtab, blob.data(), tbytes, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_idx, sidx.data(), n2 * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_p, sp.data(), n2 * sizeof(double2), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_off, count.data(), (nboxes + 1) * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "plan upload");
+    }
+    unsigned char *base = (unsigned char *)p->dtab;
+    p->tb.z = (const double *)(base + oz);
+    p->tb.lam = (const double *)(base + olam);
+    p->tb.M = (const double *)(base + oM);
+    p->tb.Tt = (const double *)(base + oT);
+    p->tb.Mf = (const float *)(base + oMf);
+    p->tb.Ttf = (const float *)(base + oTf);
+    p->geom.N = N;
+    p->geom.L = L;
+    p->geom.q = q;
+    p->geom.s = s;
+    p->geom.lm = lm;
+    p->geom.rho_scale = std::sqrt(2.0) / 2.0 * N;
+    *out = p;
+    return FIO_OK;
+}
+
+int fio_set_phase(fio_plan_t plan, const fio_phase_t *phase) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if ((rc = validate_phase(phase))) return rc;
+    plan->phase = *phase;
+    return FIO_OK;
+}
+
+int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!info) return fail(FIO_EINVAL, "info is NULL");
+    info->N = plan->N;
+    info->q = plan->q;
+    info->L = plan->L;
+    info->s = plan->s;
+    info->lm = plan->lm;
+    info->dtype = plan->dtype;
+    info->n_pairs = (int64_t)plan->N * plan->N;
+    info->weights_per_level = (int64_t)plan->N * plan->N * plan->q * plan->q;
+    info->workspace_bytes = (int64_t)plan->total_bytes;
+    info->max_box_sources = plan->max_box;
+    return FIO_OK;
+}
+
+// Forward pipeline for one right-hand side; stops after `last_stage`
+// (-1: run to the potentials).  Returns the buffer holding the last
+// stage's weights through *wlast.
+static int run_forward(fio_plan_t p, const void *f, void *u, int last_stage, void **wlast, hipStream_t st) {
+    const PhaseDev ph = to_dev(&p->phase);
+    Sources src{p->d_idx, p->d_p, p->d_off};
+    void *a = p->w0, *b = p->w1;
+    int stage = 0;
+    hipError_t e;
+    {
+        Timed tm(p, FIO_K_INIT, st);
+        e = launch_init(p->dtype, p->geom, ph, p->tb, src, f, a, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    if (last_stage == stage) {
+        *wlast = a;
+        return FIO_OK;
+    }
+    for (int l = p->s + 1; l <= p->lm; ++l) {
+        ++stage;
+        {
+        Timed tm(p, FIO_K_PLEVEL, st);
+        e = launch_plevel(p->dtype, p->geom, ph, p->tb, l, a, b, st);
+    }
+        if (e != hipSuccess) return hip_fail(e, "p-level launch");
+        std::swap(a, b);
+        if (last_stage == stage) {
+            *wlast = a;
+            return FIO_OK;
+        }
+    }
+    ++stage;
+    {
+        Timed tm(p, FIO_K_SWITCH, st);
+        e = launch_switch(p->dtype, p->geom, ph, p->tb, a, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "switch launch");
+    if (last_stage == stage) {
+        *wlast = a;
+        return FIO_OK;
+    }
+    for (int l = p->lm + 1; l <= p->L - p->s; ++l) {
+        ++stage;
+        {
+        Timed tm(p, FIO_K_XLEVEL, st);
+        e = launch_xlevel(p->dtype, p->geom, ph, p->tb, l, a, b, st);
+    }
+        if (e != hipSuccess) return hip_fail(e, "x-level launch");
+        std::swap(a, b);
+        if (last_stage == stage) {
+            *wlast = a;
+            return FIO_OK;
+        }
+    }
+    if (last_stage >= 0) return fail(FIO_EINVAL, "stage %d out of range (last is %d)", last_stage, stage);
+    {
+        Timed tm(p, FIO_K_TERM, st);
+        e = launch_term(p->dtype, p->geom, ph, p->tb, a, u, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "termination launch");
+    return FIO_OK;
+}
+
+static int run_adjoint(fio_plan_t p, const void *u, void *f, hipStream_t st) {
+    const PhaseDev ph = to_dev(&p->phase);
+    Sources src{p->d_idx, p->d_p, p->d_off};
+    void *a = p->w0, *b = p->w1;
+    hipError_t e;
+    {
+        Timed tm(p, FIO_K_TERM_ADJ, st);
+        e = launch_term_adj(p->dtype, p->geom, ph, p->tb, u, a, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "termination^H launch");
+    for (int l = p->L - p->s; l >= p->lm + 1; --l) {
+        {
+        Timed tm(p, FIO_K_XLEVEL_ADJ, st);
+        e = launch_xlevel_adj(p->dtype, p->geom, ph, p->tb, l, a, b, st);
+    }
+        if (e != hipSuccess) return hip_fail(e, "x-level^H launch");
+        std::swap(a, b);
+    }
+    {
+        Timed tm(p, FIO_K_SWITCH_ADJ, st);
+        e = launch_switch_adj(p->dtype, p->geom, ph, p->tb, a, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "switch^H launch");
+    for (int l = p->lm; l >= p->s + 1; --l) {
+        {
+        Timed tm(p, FIO_K_PLEVEL_ADJ, st);
+        e = launch_plevel_adj(p->dtype, p->geom, ph, p->tb, l, a, b, st);
+    }
+        if (e != hipSuccess) return hip_fail(e, "p-level^H launch");
+        std::swap(a, b);
+    }
+    {
+        Timed tm(p, FIO_K_INIT_ADJ, st);
+        e = launch_init_adj(p->dtype, p->geom, ph, p->tb, src, a, f, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "initialisation^H launch");
+    return FIO_OK;
+}
+
+int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream) {
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!f || !u) return fail(FIO_EINVAL, "f and u must be non-NULL device pointers");
+    if (nrhs < 1) return fail(FIO_EINVAL, "nrhs must be >= 1 (got %d)", nrhs);
+    if (f == u) return fail(FIO_EINVAL, "f and u must not overlap");
+    if ((rc = set_device(plan))) return rc;
+    const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
+    hipStream_t st = (hipStream_t)stream;
+    for (int r = 0; r < nrhs; ++r) {
+        rc = run_forward(plan, (const char *)f + r * step, (char *)u + r * step, -1, nullptr, st);
+        if (rc) return rc;
+    }
+    return FIO_OK;
+}
+
+int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, void *stream) {
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!f || !u) return fail(FIO_EINVAL, "u and f must be non-NULL device pointers");
+    if (nrhs < 1) return fail(FIO_EINVAL, "nrhs must be >= 1 (got %d)", nrhs);
+    if (f == u) return fail(FIO_EINVAL, "u and f must not overlap");
+    if ((rc = set_device(plan))) return rc;
+    const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
+    hipStream_t st = (hipStream_t)stream;
+    for (int r = 0; r < nrhs; ++r) {
+        rc = run_adjoint(plan, (const char *)u + r * step, (char *)f + r * step, st);
+        if (rc) return rc;
+    }
+    return FIO_OK;
+}
+
+int fio_debug_stage(fio_plan_t plan, const void *f, int stage, void *weights, void *stream) {
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!f || !weights) return fail(FIO_EINVAL, "f and weights must be non-NULL device pointers");
+    const int nstages = plan->L - 2 * plan->s + 2;
+    if (stage < 0 || stage >= nstages) return fail(FIO_EINVAL, "stage must be in [0, %d) (got %d)", nstages, stage);
+    if ((rc = set_device(plan))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    void *wl = nullptr;
+    if ((rc = run_forward(plan, f, nullptr, stage, &wl, st))) return rc;
+    hipError_t e = hipMemcpyAsync(weights, wl, plan->wbytes, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "weights copy");
+    return FIO_OK;
+}
+
+int fio_profile_enable(fio_plan_t plan, int enable) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    plan->prof = enable != 0;
+    return FIO_OK;
+}
+
+int fio_profile_read(fio_plan_t plan, double *ms, int64_t *launches, int n) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!ms || !launches || n < 0) return fail(FIO_EINVAL, "ms and launches must be non-NULL");
+    for (int k = 0; k < n; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (size_t i = 0; i < plan->ev_used; ++i) {
+        hipError_t e = hipEventSynchronize(plan->ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, plan->ev[2 * i], plan->ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        const int k = plan->ev_kind[i];
+        if (k < n) {
+            ms[k] += t;
+            launches[k] += 1;
+        }
+    }
+    plan->ev_used = 0;
+    return FIO_OK;
+}
+
+int fio_destroy(fio_plan_t plan) {
+    if (!plan) return FIO_OK;
+    const int dev = plan->device;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+    return FIO_OK;
+}
+
+}  // extern "C"

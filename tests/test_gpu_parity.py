@@ -1,0 +1,196 @@
+"""Parity of the HIP butterfly (through the C ABI) with the FP64 oracle.
+
+Tolerances (relative, over all outputs of a case):
+* FP64 path (complex128): 1e-10.  Both sides compute the same formulas in
+  FP64; the differences are rounding order and the factorised phase
+  rho(p1) * Phi(x, e(theta)) vs. Phi(x, k(p)), ~1e-13 cycles on phases of
+  ~N cycles, amplified by the O(1) Lebesgue constants of the levels.
+* FP32 path (complex64): see FP32_TOL; the exponentials of the FP64-reduced
+  phases are taken in FP32 (abs. error ~1e-6) and the contractions round to
+  FP32 (2^-24 per operation, ~q terms per pass), accumulated over the
+  2 + levels steps of the pass.
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct as D
+from oracle.butterfly import ButterflyModel
+from workloads import white_noise
+
+from gpu_helpers import rel_l2, rel_max, weights_to_oracle
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 2e-5
+
+# (N, q, phase, s, lm)
+CASES = [
+    (8, 5, D.Phase(), None, None),                        # smallest N: s=1, lm=1
+    (16, 3, D.Phase(), None, None),                       # smallest q, no recursion levels
+    (32, 5, D.Phase(), None, None),                       # C0 geometry (L odd, s=2, lm=2)
+    (32, 7, D.Phase(kind=D.FOURIER), 1, 2),               # p-level 2, x-levels 3, 4
+    (32, 6, D.Phase(a1=1.1, a2=0.9, eta1=0.2, eta2=0.1), 1, 3),  # even q, other switch level
+    (64, 9, D.Phase(), 2, None),                          # p-level 3, x-level 4
+    (64, 5, D.Phase(), 0, None),                          # s = 0: Sec. 4 verbatim
+    (128, 7, D.Phase(a1=0.85, a2=1.15), None, None),      # L odd, x-level 4
+    (16, 16, D.Phase(), None, None),                      # largest q
+]
+
+
+def _ids(c):
+    N, q, ph, s, lm = c
+    return f"N{N}-q{q}-k{ph.kind}-s{s}-lm{lm}"
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_forward(N, q, ph, s, lm, seed):
+    m = ButterflyModel(N, q, ph, s=s, lm=lm)
+    u, lev = m.apply(white_noise(N, seed), return_levels=True)
+    return m, u, lev
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_adjoint(N, q, ph, s, lm, seed):
+    m = ButterflyModel(N, q, ph, s=s, lm=lm)
+    return m.adjoint(white_noise(N, seed))
+
+
+def _plan(N, q, ph, s, lm, dtype):
+    import paper_0809_0719_amd as fio
+    return fio.Plan(N, q, fio.Phase(ph.kind, ph.a1, ph.a2, ph.eta1, ph.eta2), s=s, lm=lm, dtype=dtype)
+
+
+def _dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_forward_parity_fp64(case):
+    N, q, ph, s, lm = case
+    _, u_ref, _ = oracle_forward(N, q, ph, s, lm, 1)
+    plan = _plan(N, q, ph, s, lm, torch.complex128)
+    u = plan.apply(_dev(white_noise(N, 1), torch.complex128)).cpu().numpy()
+    e2, em = rel_l2(u, u_ref), rel_max(u, u_ref)
+    print(f"forward fp64 {case}: rel_l2 {e2:.2e} rel_max {em:.2e}")
+    assert e2 <= FP64_TOL and em <= FP64_TOL
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_forward_parity_fp32(case):
+    N, q, ph, s, lm = case
+    _, u_ref, _ = oracle_forward(N, q, ph, s, lm, 1)
+    plan = _plan(N, q, ph, s, lm, torch.complex64)
+    u = plan.apply(_dev(white_noise(N, 1), torch.complex64)).cpu().numpy()
+    e2, em = rel_l2(u, u_ref), rel_max(u, u_ref)
+    print(f"forward fp32 {case}: rel_l2 {e2:.2e} rel_max {em:.2e}")
+    assert e2 <= FP32_TOL and em <= 4 * FP32_TOL
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_adjoint_parity_fp64(case):
+    N, q, ph, s, lm = case
+    f_ref = oracle_adjoint(N, q, ph, s, lm, 2)
+    plan = _plan(N, q, ph, s, lm, torch.complex128)
+    f = plan.adjoint(_dev(white_noise(N, 2), torch.complex128)).cpu().numpy()
+    e2, em = rel_l2(f, f_ref), rel_max(f, f_ref)
+    print(f"adjoint fp64 {case}: rel_l2 {e2:.2e} rel_max {em:.2e}")
+    assert e2 <= FP64_TOL and em <= FP64_TOL
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_adjoint_parity_fp32(case):
+    N, q, ph, s, lm = case
+    f_ref = oracle_adjoint(N, q, ph, s, lm, 2)
+    plan = _plan(N, q, ph, s, lm, torch.complex64)
+    f = plan.adjoint(_dev(white_noise(N, 2), torch.complex64)).cpu().numpy()
+    e2, em = rel_l2(f, f_ref), rel_max(f, f_ref)
+    print(f"adjoint fp32 {case}: rel_l2 {e2:.2e} rel_max {em:.2e}")
+    assert e2 <= FP32_TOL and em <= 4 * FP32_TOL
+
+
+@pytest.mark.parametrize("case", [CASES[3], CASES[5], CASES[7]], ids=_ids)
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_every_stage_matches_the_oracle(case, dtype):
+    N, q, ph, s, lm = case
+    m, _, lev = oracle_forward(N, q, ph, s, lm, 1)
+    keys = ["init"] + [("p", l) for l in range(m.s + 1, m.lm + 1)] + ["switch"] + \
+           [("x", l) for l in range(m.lm + 1, m.L - m.s + 1)]
+    plan = _plan(N, q, ph, s, lm, dtype)
+    assert plan.n_stages == len(keys)
+    f = _dev(white_noise(N, 1), dtype)
+    tol = FP64_TOL if dtype == torch.complex128 else FP32_TOL
+    for st, key in enumerate(keys):
+        w = weights_to_oracle(plan.debug_stage(f, st).cpu().numpy(), N, q, plan.stage_level(st))
+        e2 = rel_l2(w, lev[key])
+        print(f"stage {st} {key}: rel_l2 {e2:.2e}")
+        assert e2 <= tol, (st, key, e2)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_dot_product_identity_and_linearity(dtype):
+    N, q = 64, 7
+    plan = _plan(N, q, D.Phase(), None, None, dtype)
+    f = _dev(white_noise(N, 3), dtype)
+    g = _dev(white_noise(N, 4), dtype)
+    u = _dev(white_noise(N, 5), dtype)
+    Bf = plan.apply(f)
+    lhs = torch.vdot(u.flatten(), Bf.flatten()).item()
+    rhs = torch.vdot(plan.adjoint(u).flatten(), f.flatten()).item()
+    tol = 1e-12 if dtype == torch.complex128 else 1e-5
+    assert abs(lhs - rhs) <= tol * abs(lhs)
+    a, b = 0.5 - 1.5j, 2.0 + 0.25j
+    lin = plan.apply(a * f + b * g) - (a * Bf + b * plan.apply(g))
+    assert lin.abs().max().item() <= (1e-12 if dtype == torch.complex128 else 1e-5) * Bf.abs().max().item()
+
+
+def test_several_right_hand_sides_and_zero_input():
+    N, q = 32, 5
+    plan = _plan(N, q, D.Phase(), None, None, torch.complex64)
+    F = np.stack([white_noise(N, 10 + r) for r in range(3)])
+    U = plan.apply(_dev(F, torch.complex64)).cpu().numpy()
+    for r in range(3):
+        one = plan.apply(_dev(F[r], torch.complex64)).cpu().numpy()
+        assert np.array_equal(U[r], one)          # same kernels, same inputs: bit-identical
+    z = plan.apply(torch.zeros(N, N, dtype=torch.complex64, device="cuda"))
+    assert z.abs().max().item() == 0.0
+
+
+def test_deterministic():
+    N, q = 64, 9
+    plan = _plan(N, q, D.Phase(), None, None, torch.complex64)
+    f = _dev(white_noise(N, 6), torch.complex64)
+    assert torch.equal(plan.apply(f), plan.apply(f))
+    assert torch.equal(plan.adjoint(f), plan.adjoint(f))
+
+
+def test_fourier_phase_approximates_fft():
+    # the butterfly with Phi = x.k approximates N^2 * IDFT(ifftshift(f)); its
+    # error equals the oracle model's (parity) and shrinks with q
+    N = 64
+    f = white_noise(N, 7)
+    ref = N * N * np.fft.ifft2(np.fft.ifftshift(f))
+    errs = []
+    for q in (9, 13):
+        plan = _plan(N, q, D.Phase(kind=D.FOURIER), 2, None, torch.complex128)
+        u = plan.apply(_dev(f, torch.complex128)).cpu().numpy()
+        errs.append(rel_l2(u, ref))
+    assert errs[1] < errs[0] / 10
+
+
+def test_bad_arguments_raise():
+    import paper_0809_0719_amd as fio
+    with pytest.raises(RuntimeError):
+        fio.Plan(48, 9)
+    with pytest.raises(RuntimeError):
+        fio.Plan(64, 9, s=4)
+    plan = fio.Plan(32, 5)
+    with pytest.raises(TypeError):
+        plan.apply(torch.zeros(32, 32, dtype=torch.complex128, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.apply(torch.zeros(16, 16, dtype=torch.complex64, device="cuda"))
+    with pytest.raises(RuntimeError):
+        plan.debug_stage(torch.zeros(32, 32, dtype=torch.complex64, device="cuda"), 99)
