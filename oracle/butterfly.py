@@ -133,6 +133,22 @@ class ButterflyModel:
             raise ValueError(f"need 0 <= s <= lm <= L-s (s={self.s}, lm={self.lm}, L={L})")
         self.z = cheb_nodes(q)
         self.k1, self.k2, self.p1, self.p2 = polar_points(N)
+        self.active = None     # {level: sorted list of (a1, a2)} when restricted
+
+    # -- which boxes A a step computes -----------------------------------
+    def boxes(self, l: int):
+        """Boxes A of T_X at level l that the steps compute (all by default)."""
+        if self.active is None:
+            n = 1 << l
+            return [(a1, a2) for a1 in range(n) for a2 in range(n)]
+        return self.active[l]
+
+    def new_level(self, l: int, nB: int):
+        """Weights of level l: a dense array, or a dict keyed by (a1, a2) when
+        only the ancestors of some target boxes are computed."""
+        if self.active is None:
+            return np.zeros((1 << l, 1 << l, nB, nB, self.q, self.q), dtype=np.complex128)
+        return {}
 
     # -- kernel values ---------------------------------------------------
     def E(self, x1, x2, k1, k2):
@@ -162,9 +178,8 @@ class ButterflyModel:
         pn2 = nodes(lB, np.arange(nB), z)                 # (nB, q)  p2 nodes
         P1 = pn1[:, None, :, None]                        # (b1, b2, t1, t2)
         P2 = pn2[None, :, None, :]
-        out = np.zeros((nA, nA, nB, nB, q, q), dtype=np.complex128)
-        for a1 in range(nA):
-            for a2 in range(nA):
+        out = self.new_level(s, nB)
+        for a1, a2 in self.boxes(s):
                 x01, x02 = centre(s, a1), centre(s, a2)
                 g = self.E(x01, x02, self.k1, self.k2) * f                 # E(x0(A),p) f(p)
                 acc = onehot @ (g[:, None] * lag)                          # sum_{p in B}
@@ -194,9 +209,8 @@ class ButterflyModel:
         pn = nodes(lB, b, z)                                                # (nB, q)
         PN1 = pn[:, None, :, None]
         PN2 = pn[None, :, None, :]
-        out = np.zeros((nA, nA, nB, nB, q, q), dtype=np.complex128)
-        for a1 in range(nA):
-            for a2 in range(nA):
+        out = self.new_level(l, nB)
+        for a1, a2 in self.boxes(l):
                 x01, x02 = centre(l, a1), centre(l, a2)
                 pre = self.E_p(x01, x02, PC1, PC2)                          # (2nB q, 2nB q)
                 pre = pre.reshape(2 * nB, q, 2 * nB, q).transpose(0, 2, 1, 3)
@@ -220,10 +234,8 @@ class ButterflyModel:
         return self.E_p(X1, X2, P1, P2)
 
     def switch(self, d: np.ndarray) -> np.ndarray:
-        nA = 1 << self.lm
-        out = np.empty_like(d)
-        for a1 in range(nA):
-            for a2 in range(nA):
+        out = self.new_level(self.lm, 1 << (self.L - self.lm))
+        for a1, a2 in self.boxes(self.lm):
                 K = self.switch_kernel(a1, a2)
                 out[a1, a2] = np.einsum("xyijkl,xykl->xyij", K, d[a1, a2], optimize=True)
         return out
@@ -245,9 +257,8 @@ class ButterflyModel:
         pc0 = centre(lB + 1, np.arange(2 * nB))                              # p0(B_c)
         PC1 = pc0[:, None, None, None]
         PC2 = pc0[None, :, None, None]
-        out = np.zeros((nA, nA, nB, nB, q, q), dtype=np.complex128)
-        for a1 in range(nA):
-            for a2 in range(nA):
+        out = self.new_level(l, nB)
+        for a1, a2 in self.boxes(l):
                 ap1, ap2 = a1 // 2, a2 // 2
                 xp1, xp2 = nodes(l - 1, ap1, z), nodes(l - 1, ap2, z)
                 pre = np.conj(self.E_p(xp1[None, None, :, None], xp2[None, None, None, :], PC1, PC2))
@@ -275,8 +286,7 @@ class ButterflyModel:
         PB1 = p0[:, None, None, None]
         PB2 = p0[None, :, None, None]
         u = np.zeros((N, N), dtype=np.complex128)
-        for a1 in range(nA):
-            for a2 in range(nA):
+        for a1, a2 in self.boxes(lA):
                 xa1, xa2 = nodes(lA, a1, z), nodes(lA, a2, z)
                 pre = np.conj(self.E_p(xa1[None, None, :, None], xa2[None, None, None, :], PB1, PB2))
                 V = np.einsum("ik,jl,xykl->xyij", Tm, Tm, pre * d[a1, a2], optimize=True)
@@ -287,9 +297,20 @@ class ButterflyModel:
         return u
 
     # -- full pass ---------------------------------------------------------
-    def apply(self, f: np.ndarray, return_levels: bool = False):
+    def apply(self, f: np.ndarray, return_levels: bool = False, targets=None):
         """u = B f.  With ``return_levels`` also returns a dict of the weights:
-        'init', ('p', l), 'switch', ('x', l)."""
+        'init', ('p', l), 'switch', ('x', l).
+
+        ``targets``: optional list of boxes (a1, a2) at level L-s of T_X; then
+        only the pairs whose A is one of their ancestors are computed (the same
+        formulas, restricted loops), u is exact only on those boxes and zero
+        elsewhere, and the levels are dicts keyed by (a1, a2)."""
+        if targets is None:
+            self.active = None
+        else:
+            top = self.L - self.s
+            self.active = {l: sorted({(a1 >> (top - l), a2 >> (top - l)) for a1, a2 in targets})
+                           for l in range(self.s, top + 1)}
         lev = {}
         d = self.init(f)
         lev["init"] = d

@@ -194,3 +194,44 @@ def test_bad_arguments_raise():
         plan.apply(torch.zeros(16, 16, dtype=torch.complex64, device="cuda"))
     with pytest.raises(RuntimeError):
         plan.debug_stage(torch.zeros(32, 32, dtype=torch.complex64, device="cuda"), 99)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_full_size_sampled_parity(dtype):
+    """The benchmark's configuration (N=1024, q=9, eq:ex1, s=3, lm=5): the
+    oracle computes the ancestor chains of a few sampled leaf boxes A (level
+    L-s) and the GPU must match it on those boxes' 64 potentials each and on
+    every stage's weights of those ancestors."""
+    N, q = 1024, 9
+    rng = np.random.default_rng(2024)
+    targets = [tuple(int(v) for v in rng.integers(0, 128, 2)) for _ in range(2)]
+    m = ButterflyModel(N, q, D.Phase())
+    f = white_noise(N, 21)
+    u_ref, lev = m.apply(f, return_levels=True, targets=targets)
+    plan = _plan(N, q, D.Phase(), None, None, dtype)
+    fd = _dev(f, dtype)
+    u = plan.apply(fd).cpu().numpy()
+    tol = FP64_TOL if dtype == torch.complex128 else FP32_TOL
+    side = 1 << m.s
+    got, ref = [], []
+    for a1, a2 in targets:
+        blk = (slice(a1 * side, (a1 + 1) * side), slice(a2 * side, (a2 + 1) * side))
+        got.append(u[blk])
+        ref.append(u_ref[blk])
+    e2 = rel_l2(np.array(got), np.array(ref))
+    print(f"full size {dtype}: potentials rel_l2 {e2:.2e}")
+    assert e2 <= tol
+    keys = ["init"] + [("p", l) for l in range(m.s + 1, m.lm + 1)] + ["switch"] + \
+           [("x", l) for l in range(m.lm + 1, m.L - m.s + 1)]
+    for st, key in enumerate(keys):
+        level = plan.stage_level(st)
+        w = plan.debug_stage(fd, st).cpu().numpy().reshape(N * N, q, q)
+        nB = 1 << (m.L - level)
+        from gpu_helpers import morton
+        bm = morton(*np.meshgrid(np.arange(nB), np.arange(nB), indexing="ij"))
+        for (a1, a2), wref in lev[key].items():
+            pair = int(morton(a1, a2)) * nB * nB + bm
+            e = rel_l2(w[pair], wref)
+            assert e <= tol, (st, key, (a1, a2), e)
+        print(f"  stage {st} {key}: ok")
+        del w

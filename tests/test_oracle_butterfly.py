@@ -108,3 +108,21 @@ def test_planted_mistakes_are_caught(mutant):
     bad = _err(32, 13, FOURIER, s=1, model=mutant)
     assert good < 1e-3
     assert bad > 100 * good, (good, bad)
+
+
+def test_restricted_targets_equal_the_full_pass():
+    # computing only the ancestor chain of some target boxes gives the same
+    # potentials on those boxes and the same weights for those ancestors
+    N, q, s = 64, 5, 2
+    m = ButterflyModel(N, q, ELLIPSE, s=s)
+    f = white_noise(N, 9)
+    u_full, lev_full = m.apply(f, return_levels=True)
+    targets = [(0, 0), (5, 11), (15, 15)]
+    u_part, lev_part = m.apply(f, return_levels=True, targets=targets)
+    m_side = 1 << s
+    for a1, a2 in targets:
+        blk = (slice(a1 * m_side, (a1 + 1) * m_side), slice(a2 * m_side, (a2 + 1) * m_side))
+        assert np.array_equal(u_part[blk], u_full[blk])
+    for key, part in lev_part.items():
+        for (a1, a2), w in part.items():
+            assert np.array_equal(w, lev_full[key][a1, a2])
