@@ -159,106 +159,132 @@ __global__ __launch_bounds__(NT) void k_init(Geom g, PhaseDev ph, Tables tb, Sou
 }
 
 // ===========================================================================
+// Butterfly blocks per workgroup for the level kernels: 8q threads per block
+// (2q per output pair), limited so the block's LDS stays near 40 KB.
+// ===========================================================================
+template <typename T, int Q, int PERBB>
+constexpr int blocks_per_wg() {
+    constexpr int byT = NT / (8 * Q);
+    constexpr int byL = 40960 / (PERBB * Q * Q * (int)sizeof(cpx<T>));
+    constexpr int b = byT < byL ? byT : byL;
+    return b < 1 ? 1 : b;
+}
+
+// ===========================================================================
 // Step 3, p-recursion (eq:alg2b) at level l: block (A_p at l-1, B at L-l)
 //   delta^{AB}_t = conj E(x0(A), p^B_t) sum_c sum_t' M_c1[t1][t'1] M_c2[t2][t'2]
 //                     E(x0(A), p^{B_c}_t') delta^{A_p B_c}_t'
 // for the four children A of A_p.  The q x q Kronecker sum over the four
 // children B_c is done one dimension at a time (Sec. 4: 6 q^3 per pair).
-// One workgroup per block; the four outputs are produced one after another
-// by all threads.
+// Each output pair gets 2q threads: in the first pass thread (c1, t'1)
+// forms its prefactored row of the two children (c1, 0), (c1, 1) in
+// registers and contracts it against M_c2 (read as LDS broadcasts); in the
+// second pass thread (t2, half) takes column t2 and produces half the rows
+// t1, remodulated and stored.
 // ===========================================================================
 template <typename T, int Q>
 __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, int level,
                                                const cpx<T> *__restrict__ win,
-                                               cpx<T> *__restrict__ wout) {
+                                               cpx<T> *__restrict__ wout, unsigned nblk) {
     constexpr int QQ = Q * Q;
-    __shared__ cpx<T> din[4 * QQ];
-    __shared__ cpx<T> v[4 * QQ];
-    __shared__ cpx<T> W[2 * QQ];
-    __shared__ T Ms[2 * QQ];
-    __shared__ double rc[2 * Q], ctc[2 * Q], stc[2 * Q];  // child nodes: rho(c1,t'1), theta(c2,t'2)
-    __shared__ double rb[Q], ctb[Q], stb[Q];              // B's own nodes
-    __shared__ double Gc[2 * Q], Gb[Q];
+    constexpr int TPO = 2 * Q;            // threads per output pair
+    constexpr int TPB = 4 * TPO;          // threads per butterfly block
+    constexpr int BPW = blocks_per_wg<T, Q, 8>();
+    constexpr int H1 = (Q + 1) / 2;
+    __shared__ T Mt[2][Q][Q];             // Mt[c][t'][t] = M_c[t][t']
+    __shared__ T Ms[2][Q][Q];             // Ms[c][t][t'] = M_c[t][t']
+    __shared__ double rc[BPW][2 * Q], ctc[BPW][2 * Q], stc[BPW][2 * Q];  // child nodes: rho(c1,t'), theta(c2,t')
+    __shared__ double rb[BPW][Q], ctb[BPW][Q], stb[BPW][Q];              // B's nodes
+    __shared__ double Gc[BPW][4][2 * Q], Gb[BPW][4][Q];
+    __shared__ cpx<T> W[BPW][4][2 * QQ];  // first-pass rows [c1][t'1][t2]
 
     const int tid = threadIdx.x;
+    const int bbl = tid / TPB, r = tid - bbl * TPB;
+    const int j = r / TPO, rr = r - j * TPO;
+    const size_t blk = (size_t)blockIdx.x * BPW + bbl;
+    const bool active = bbl < BPW && blk < nblk;
     const int lB = g.L - level;
-    const size_t blk = blockIdx.x;
-    const uint32_t mB = (uint32_t)(blk & (((size_t)1 << (2 * lB)) - 1));
-    const uint32_t mAp = (uint32_t)(blk >> (2 * lB));
-    int b1, b2, ap1, ap2;
-    morton_decode(mB, b1, b2);
-    morton_decode(mAp, ap1, ap2);
+    const size_t nBl = (size_t)1 << (2 * lB);
 
-    const cpx<T> *src = win + blk * (4 * QQ);
-    for (int i = tid; i < 4 * QQ; i += NT) din[i] = src[i];
     const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) Ms[i] = Mg[i];
-    if (tid < 2 * Q) {
-        const int c = tid / Q, t = tid - c * Q;
-        const double z = tb.z[t];
-        rc[tid] = g.rho_scale * box_node(2 * b1 + c, lB + 1, z);
-        double s_, c_;
-        sincospi(2.0 * box_node(2 * b2 + c, lB + 1, z), &s_, &c_);
-        ctc[tid] = c_;
-        stc[tid] = s_;
-    } else if (tid >= 64 && tid < 64 + Q) {
-        const int t = tid - 64;
-        const double z = tb.z[t];
-        rb[t] = g.rho_scale * box_node(b1, lB, z);
-        double s_, c_;
-        sincospi(2.0 * box_node(b2, lB, z), &s_, &c_);
-        ctb[t] = c_;
-        stb[t] = s_;
+    for (int i = tid; i < 2 * QQ; i += NT) {
+        const int c = i / QQ, t = (i - c * QQ) / Q, tp = i - c * QQ - t * Q;
+        Ms[c][t][tp] = Mg[i];
+        Mt[c][tp][t] = Mg[i];
+    }
+    uint32_t mB = 0, mAp = 0;
+    int b1 = 0, b2 = 0, ap1 = 0, ap2 = 0;
+    if (active) {
+        mB = (uint32_t)(blk & (nBl - 1));
+        mAp = (uint32_t)(blk >> (2 * lB));
+        morton_decode(mB, b1, b2);
+        morton_decode(mAp, ap1, ap2);
+        if (j == 0) {
+            const int c = rr / Q, t = rr - c * Q;
+            const double z = tb.z[t];
+            rc[bbl][rr] = g.rho_scale * box_node(2 * b1 + c, lB + 1, z);
+            double s_, c_;
+            sincospi(2.0 * box_node(2 * b2 + c, lB + 1, z), &s_, &c_);
+            ctc[bbl][rr] = c_;
+            stc[bbl][rr] = s_;
+        } else if (j == 1 && rr < Q) {
+            const double z = tb.z[rr];
+            rb[bbl][rr] = g.rho_scale * box_node(b1, lB, z);
+            double s_, c_;
+            sincospi(2.0 * box_node(b2, lB, z), &s_, &c_);
+            ctb[bbl][rr] = c_;
+            stb[bbl][rr] = s_;
+        }
     }
     __syncthreads();
-
-    const size_t nBl = (size_t)1 << (2 * lB);
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t mA = 4 * mAp + j;
-        const int a1 = 2 * ap1 + (j >> 1), a2 = 2 * ap2 + (j & 1);
+    const int a1 = 2 * ap1 + (j >> 1), a2 = 2 * ap2 + (j & 1);
+    if (active) {
         const XP xp = make_xp(ph, box_centre(a1, level), box_centre(a2, level));
-        if (tid < 2 * Q) Gc[tid] = phase_dir(xp, ctc[tid], stc[tid]);
-        else if (tid >= 64 && tid < 64 + Q) Gb[tid - 64] = phase_dir(xp, ctb[tid - 64], stb[tid - 64]);
-        __syncthreads();
-        // prefactor E(x0(A), p^{B_c}_t') delta^{A_p B_c}_t'
-        for (int i = tid; i < 4 * QQ; i += NT) {
-            const int c = i / QQ, t = i - c * QQ;
-            const int c1 = c >> 1, c2 = c & 1;
-            const int tp1 = t / Q, tp2 = t - tp1 * Q;
-            const cpx<T> e = cis<T>(rc[c1 * Q + tp1] * Gc[c2 * Q + tp2]);
-            v[i] = cmul(e, din[i]);
-        }
-        __syncthreads();
-        // pass 1 (second dimension): W[c1][t'1][t2] = sum_c2 sum_t'2 M_c2[t2][t'2] v[c1 c2][t'1][t'2]
-        for (int i = tid; i < 2 * QQ; i += NT) {
-            const int c1 = i / QQ, r = i - c1 * QQ;
-            const int tp1 = r / Q, t2 = r - tp1 * Q;
-            cpx<T> acc = {(T)0, (T)0};
+        Gc[bbl][j][rr] = phase_dir(xp, ctc[bbl][rr], stc[bbl][rr]);
+        if (rr < Q) Gb[bbl][j][rr] = phase_dir(xp, ctb[bbl][rr], stb[bbl][rr]);
+    }
+    __syncthreads();
+    if (active) {
+        // first pass: row (c1, t'1)
+        const int c1 = rr / Q, tp1 = rr - c1 * Q;
+        const double rho = rc[bbl][rr];
+        cpx<T> acc[Q];
 #pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2) {
-                const cpx<T> *vv = v + (2 * c1 + c2) * QQ + tp1 * Q;
-                const T *m = Ms + c2 * QQ + t2 * Q;
+        for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
 #pragma unroll
-                for (int tp2 = 0; tp2 < Q; ++tp2) crfma(acc, m[tp2], vv[tp2]);
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const cpx<T> *src = win + (blk * 4 + 2 * c1 + c2) * QQ + tp1 * Q;
+#pragma unroll
+            for (int tp2 = 0; tp2 < Q; ++tp2) {
+                const cpx<T> v = cmul(cis<T>(rho * Gc[bbl][j][c2 * Q + tp2]), src[tp2]);
+#pragma unroll
+                for (int t2 = 0; t2 < Q; ++t2) crfma(acc[t2], Mt[c2][tp2][t2], v);
             }
-            W[i] = acc;
         }
-        __syncthreads();
-        // pass 2 (first dimension) + remodulation conj E(x0(A), p^B_t)
-        cpx<T> *dst = wout + ((size_t)mA * nBl + mB) * QQ;
-        for (int i = tid; i < QQ; i += NT) {
-            const int t1 = i / Q, t2 = i - t1 * Q;
-            cpx<T> acc = {(T)0, (T)0};
 #pragma unroll
-            for (int c1 = 0; c1 < 2; ++c1) {
-                const T *m = Ms + c1 * QQ + t1 * Q;
+        for (int t2 = 0; t2 < Q; ++t2) W[bbl][j][rr * Q + t2] = acc[t2];
+    }
+    __syncthreads();
+    if (active) {
+        // second pass: column t2, rows t1 of one half, then remodulation
+        const int h = rr / Q, t2 = rr - h * Q;
+        cpx<T> col[2 * Q];
 #pragma unroll
-                for (int tp1 = 0; tp1 < Q; ++tp1) crfma(acc, m[tp1], W[c1 * QQ + tp1 * Q + t2]);
+        for (int k = 0; k < 2 * Q; ++k) col[k] = W[bbl][j][k * Q + t2];
+        const double G = Gb[bbl][j][t2];
+        cpx<T> *dst = wout + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
+#pragma unroll
+        for (int k = 0; k < H1; ++k) {
+            const int t1 = h * H1 + k;
+            if (t1 < Q) {
+                cpx<T> o = {(T)0, (T)0};
+#pragma unroll
+                for (int c1 = 0; c1 < 2; ++c1)
+#pragma unroll
+                    for (int tp1 = 0; tp1 < Q; ++tp1) crfma(o, Ms[c1][t1][tp1], col[c1 * Q + tp1]);
+                dst[t1 * Q + t2] = cmulc(o, cis<T>(rb[bbl][t1] * G));
             }
-            const cpx<T> e = cis<T>(rb[t1] * Gb[t2]);
-            dst[i] = cmulc(acc, e);
         }
-        __syncthreads();
     }
 }
 
@@ -344,118 +370,137 @@ __global__ __launch_bounds__(NT) void k_switch(Geom g, PhaseDev ph, Tables tb, c
 //   delta^{AB}_t = sum_c E(x^A_t, p0(B_c)) sum_t' M_a1[t'1][t1] M_a2[t'2][t2]
 //                    conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t'
 // for the four children A = (a1, a2) of A_p.  The prefactor depends only on
-// (A_p, B_c) and is applied once per block.
+// (A_p, B_c) and is applied once per block; the first (second-dimension)
+// pass depends on A only through a2, so it is shared by the children with
+// the same a2.  Threads: prefactor (c, t'1) rows; first pass (a2, c, t'1)
+// rows; second pass (A, t2, half) columns with the remodulation per B_c.
 // ===========================================================================
 template <typename T, int Q>
 __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, int level,
                                                const cpx<T> *__restrict__ win,
-                                               cpx<T> *__restrict__ wout) {
+                                               cpx<T> *__restrict__ wout, unsigned nblk) {
     constexpr int QQ = Q * Q;
-    __shared__ cpx<T> v[4 * QQ];
-    __shared__ cpx<T> Y[4 * QQ];
-    __shared__ T Ms[2 * QQ];
-    __shared__ double sx1[Q], cx1[Q], sx2[Q], cx2[Q];   // sin/cos(2 pi x) at the nodes of the current box
-    __shared__ double r0c[2], ct0[2], st0[2];           // p0(B_c): rho(c1), theta(c2)
+    constexpr int TPB = 8 * Q;
+    constexpr int BPW = blocks_per_wg<T, Q, 12>();
+    constexpr int H1 = (Q + 1) / 2;
+    __shared__ T Ms[2][Q][Q];                       // Ms[a][t'][t] = M_a[t'][t]
+    __shared__ cpx<T> v[BPW][4][QQ];                // prefactored inputs [c][t'1][t'2]
+    __shared__ cpx<T> Y[BPW][2][4][QQ];             // first pass [a2][c][t'1][t2]
+    __shared__ double sp[BPW][2][Q], cp[BPW][2][Q];        // sin/cos(2 pi x) at A_p's nodes, per dim
+    __shared__ double sj[BPW][2][2][Q], cj[BPW][2][2][Q];  // at the children's nodes [dim][a][t]
+    __shared__ double r0c[BPW][2], ct0[BPW][2], st0[BPW][2];
 
     const int tid = threadIdx.x;
+    const int bbl = tid / TPB, rr = tid - bbl * TPB;
+    const size_t blk = (size_t)blockIdx.x * BPW + bbl;
+    const bool active = bbl < BPW && blk < nblk;
     const int lB = g.L - level;
-    const size_t blk = blockIdx.x;
-    const uint32_t mB = (uint32_t)(blk & (((size_t)1 << (2 * lB)) - 1));
-    const uint32_t mAp = (uint32_t)(blk >> (2 * lB));
-    int b1, b2, ap1, ap2;
-    morton_decode(mB, b1, b2);
-    morton_decode(mAp, ap1, ap2);
+    const size_t nBl = (size_t)1 << (2 * lB);
     const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
 
     const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) Ms[i] = Mg[i];
-    if (tid < 2) {
-        r0c[tid] = g.rho_scale * box_centre(2 * b1 + tid, lB + 1);
-        double s_, c_;
-        sincospi(2.0 * box_centre(2 * b2 + tid, lB + 1), &s_, &c_);
-        ct0[tid] = c_;
-        st0[tid] = s_;
-    } else if (tid >= 64 && tid < 64 + Q) {
-        const int t = tid - 64;
-        double s_ = 0, c_ = 1;
-        if (ell) sincospi(2.0 * box_node(ap1, level - 1, tb.z[t]), &s_, &c_);
-        sx1[t] = s_;
-        cx1[t] = c_;
-    } else if (tid >= 128 && tid < 128 + Q) {
-        const int t = tid - 128;
-        double s_ = 0, c_ = 1;
-        if (ell) sincospi(2.0 * box_node(ap2, level - 1, tb.z[t]), &s_, &c_);
-        sx2[t] = s_;
-        cx2[t] = c_;
-    }
-    __syncthreads();
-    // prefactor conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t'; thread <-> (c2, t')
-    const cpx<T> *src = win + blk * (4 * QQ);
-    for (int i = tid; i < 2 * QQ; i += NT) {
-        const int c2 = i / QQ, tp = i - c2 * QQ;
-        const int tp1 = tp / Q, tp2 = tp - tp1 * Q;
-        const XP xp = make_xp_sc(ph, box_node(ap1, level - 1, tb.z[tp1]), box_node(ap2, level - 1, tb.z[tp2]),
-                                 sx1[tp1], cx1[tp1], sx2[tp2], cx2[tp2]);
-        const double G = phase_dir(xp, ct0[c2], st0[c2]);
-#pragma unroll
-        for (int c1 = 0; c1 < 2; ++c1) {
-            const int c = 2 * c1 + c2;
-            v[c * QQ + tp] = cmulc(src[c * QQ + tp], cis<T>(r0c[c1] * G));
+    for (int i = tid; i < 2 * QQ; i += NT) (&Ms[0][0][0])[i] = Mg[i];
+    uint32_t mB = 0, mAp = 0;
+    int b1 = 0, b2 = 0, ap1 = 0, ap2 = 0;
+    if (active) {
+        mB = (uint32_t)(blk & (nBl - 1));
+        mAp = (uint32_t)(blk >> (2 * lB));
+        morton_decode(mB, b1, b2);
+        morton_decode(mAp, ap1, ap2);
+        if (rr < 2 * Q) {                      // A_p's nodes, dim rr / Q
+            const int d = rr / Q, t = rr - d * Q;
+            double s_ = 0, c_ = 1;
+            if (ell) sincospi(2.0 * box_node(d ? ap2 : ap1, level - 1, tb.z[t]), &s_, &c_);
+            sp[bbl][d][t] = s_;
+            cp[bbl][d][t] = c_;
+        } else if (rr < 6 * Q) {               // children's nodes, [dim][a][t]
+            const int k = rr - 2 * Q, d = k / (2 * Q), a = (k / Q) & 1, t = k % Q;
+            double s_ = 0, c_ = 1;
+            if (ell) sincospi(2.0 * box_node(2 * (d ? ap2 : ap1) + a, level, tb.z[t]), &s_, &c_);
+            sj[bbl][d][a][t] = s_;
+            cj[bbl][d][a][t] = c_;
+        } else if (rr < 6 * Q + 2) {           // p0(B_c): rho by c1, theta by c2
+            const int c = rr - 6 * Q;
+            r0c[bbl][c] = g.rho_scale * box_centre(2 * b1 + c, lB + 1);
+            double s_, c_;
+            sincospi(2.0 * box_centre(2 * b2 + c, lB + 1), &s_, &c_);
+            ct0[bbl][c] = c_;
+            st0[bbl][c] = s_;
         }
     }
     __syncthreads();
-
-    const size_t nBl = (size_t)1 << (2 * lB);
-    for (int j = 0; j < 4; ++j) {
-        const int j1 = j >> 1, j2 = j & 1;
-        const uint32_t mA = 4 * mAp + j;
+    // prefactor conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t': row (c, t'1)
+    if (active && rr < 4 * Q) {
+        const int c = rr / Q, tp1 = rr - c * Q;
+        const int c1 = c >> 1, c2 = c & 1;
+        const cpx<T> *src = win + (blk * 4 + c) * QQ + tp1 * Q;
+        const double xa1 = box_node(ap1, level - 1, tb.z[tp1]);
+#pragma unroll
+        for (int tp2 = 0; tp2 < Q; ++tp2) {
+            const XP xp = make_xp_sc(ph, xa1, box_node(ap2, level - 1, tb.z[tp2]), sp[bbl][0][tp1],
+                                     cp[bbl][0][tp1], sp[bbl][1][tp2], cp[bbl][1][tp2]);
+            const double G = phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]);
+            v[bbl][c][tp1 * Q + tp2] = cmulc(src[tp2], cis<T>(r0c[bbl][c1] * G));
+        }
+    }
+    __syncthreads();
+    // first pass (second dimension): Y[a2][c][t'1][t2] = sum_t'2 M_a2[t'2][t2] v[c][t'1][t'2]
+    if (active) {
+        const int a2c = rr / (4 * Q), k = rr - a2c * 4 * Q;
+        const int c = k / Q, tp1 = k - c * Q;
+        cpx<T> acc[Q];
+#pragma unroll
+        for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
+#pragma unroll
+        for (int tp2 = 0; tp2 < Q; ++tp2) {
+            const cpx<T> vv = v[bbl][c][tp1 * Q + tp2];
+#pragma unroll
+            for (int t2 = 0; t2 < Q; ++t2) crfma(acc[t2], Ms[a2c][tp2][t2], vv);
+        }
+#pragma unroll
+        for (int t2 = 0; t2 < Q; ++t2) Y[bbl][a2c][c][tp1 * Q + t2] = acc[t2];
+    }
+    __syncthreads();
+    // second pass (first dimension), remodulation E(x^A_t, p0(B_c)), sum over c
+    if (active) {
+        const int jj = rr / (2 * Q), k = rr - jj * 2 * Q;
+        const int h = k / Q, t2 = k - h * Q;
+        const int j1 = jj >> 1, j2 = jj & 1;
         const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
-        // sin/cos tables for the nodes of A (reuse the A_p slots after a barrier)
-        if (tid < Q) {
-            double s_ = 0, c_ = 1;
-            if (ell) sincospi(2.0 * box_node(a1, level, tb.z[tid]), &s_, &c_);
-            sx1[tid] = s_;
-            cx1[tid] = c_;
-        } else if (tid >= 64 && tid < 64 + Q) {
-            const int t = tid - 64;
-            double s_ = 0, c_ = 1;
-            if (ell) sincospi(2.0 * box_node(a2, level, tb.z[t]), &s_, &c_);
-            sx2[t] = s_;
-            cx2[t] = c_;
+        double G0[H1], G1[H1];
+        cpx<T> out[H1];
+        const double xb2 = box_node(a2, level, tb.z[t2]);
+#pragma unroll
+        for (int kk = 0; kk < H1; ++kk) {
+            const int t1 = min(h * H1 + kk, Q - 1);
+            const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), xb2, sj[bbl][0][j1][t1],
+                                     cj[bbl][0][j1][t1], sj[bbl][1][j2][t2], cj[bbl][1][j2][t2]);
+            G0[kk] = phase_dir(xp, ct0[bbl][0], st0[bbl][0]);
+            G1[kk] = phase_dir(xp, ct0[bbl][1], st0[bbl][1]);
+            out[kk] = {(T)0, (T)0};
         }
-        // pass 1 (second dimension): Y[c][t'1][t2] = sum_t'2 M_j2[t'2][t2] v[c][t'1][t'2]
-        for (int i = tid; i < 4 * QQ; i += NT) {
-            const int c = i / QQ, r = i - c * QQ;
-            const int tp1 = r / Q, t2 = r - tp1 * Q;
-            const cpx<T> *vv = v + c * QQ + tp1 * Q;
-            const T *m = Ms + j2 * QQ + t2;
-            cpx<T> acc = {(T)0, (T)0};
+#pragma unroll 1
+        for (int c = 0; c < 4; ++c) {
+            const int c1 = c >> 1, c2 = c & 1;
+            cpx<T> col[Q];
 #pragma unroll
-            for (int tp2 = 0; tp2 < Q; ++tp2) crfma(acc, m[tp2 * Q], vv[tp2]);
-            Y[i] = acc;
-        }
-        __syncthreads();
-        // pass 2 (first dimension), remodulation E(x^A_t, p0(B_c)), sum over c
-        cpx<T> *dst = wout + ((size_t)mA * nBl + mB) * QQ;
-        for (int i = tid; i < QQ; i += NT) {
-            const int t1 = i / Q, t2 = i - t1 * Q;
-            const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[t2]),
-                                     sx1[t1], cx1[t1], sx2[t2], cx2[t2]);
-            const double G0 = phase_dir(xp, ct0[0], st0[0]);
-            const double G1 = phase_dir(xp, ct0[1], st0[1]);
-            cpx<T> out = {(T)0, (T)0};
+            for (int tp1 = 0; tp1 < Q; ++tp1) col[tp1] = Y[bbl][j2][c][tp1 * Q + t2];
+            const double rho = r0c[bbl][c1];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int c1 = c >> 1, c2 = c & 1;
-                const T *m = Ms + j1 * QQ + t1;
-                cpx<T> acc = {(T)0, (T)0};
+            for (int kk = 0; kk < H1; ++kk) {
+                const int t1 = min(h * H1 + kk, Q - 1);
+                cpx<T> z = {(T)0, (T)0};
 #pragma unroll
-                for (int tp1 = 0; tp1 < Q; ++tp1) crfma(acc, m[tp1 * Q], Y[c * QQ + tp1 * Q + t2]);
-                cfma(out, cis<T>(r0c[c1] * (c2 ? G1 : G0)), acc);
+                for (int tp1 = 0; tp1 < Q; ++tp1) crfma(z, Ms[j1][tp1][t1], col[tp1]);
+                cfma(out[kk], cis<T>(rho * (c2 ? G1[kk] : G0[kk])), z);
             }
-            dst[i] = out;
         }
-        __syncthreads();
+        cpx<T> *dst = wout + ((size_t)(4 * mAp + jj) * nBl + mB) * QQ;
+#pragma unroll
+        for (int kk = 0; kk < H1; ++kk) {
+            const int t1 = h * H1 + kk;
+            if (t1 < Q) dst[t1 * Q + t2] = out[kk];
+        }
     }
 }
 
@@ -658,119 +703,139 @@ __global__ __launch_bounds__(NT) void k_term_adj(Geom g, PhaseDev ph, Tables tb,
 // x-level^H at level l: from the outputs (A_j, B) back to the inputs (A_p, B_c)
 //   delta^{A_p B_c}_t' = E(x^{A_p}_t', p0(B_c)) sum_j sum_t M_j1[t'1][t1] M_j2[t'2][t2]
 //                          conj E(x^{A_j}_t, p0(B_c)) delta^{A_j B}_t
+// First pass: thread (j1, c2, t1, j2) forms row t1 of conj E delta for its
+// child (j1, j2) and both c1, contracts over t2 with M_j2, and the two j2
+// partial rows are added through a lane exchange.  Second pass: thread
+// (c, t'2, half) contracts over t1 with M_j1, sums j1 and applies the factor
+// E(x^{A_p}_t', p0(B_c)).
 template <typename T, int Q>
 __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables tb, int level,
                                                    const cpx<T> *__restrict__ win,
-                                                   cpx<T> *__restrict__ wout) {
+                                                   cpx<T> *__restrict__ wout, unsigned nblk) {
     constexpr int QQ = Q * Q;
-    __shared__ cpx<T> v[4 * QQ];    // one output pair A_j, split per c by the remodulation
-    __shared__ cpx<T> Y[4 * QQ];
-    __shared__ cpx<T> acc4[4 * QQ]; // accumulated over j, per c
-    __shared__ T Ms[2 * QQ];
-    __shared__ double sx1[Q], cx1[Q], sx2[Q], cx2[Q];
-    __shared__ double r0c[2], ct0[2], st0[2];
+    constexpr int TPB = 8 * Q;
+    constexpr int BPW = blocks_per_wg<T, Q, 8>();
+    constexpr int H1 = (Q + 1) / 2;
+    __shared__ T Ms[2][Q][Q];                       // Ms[a][t'][t] = M_a[t'][t]
+    __shared__ cpx<T> Y[BPW][2][4][QQ];             // [j1][c][t1][t'2]
+    __shared__ double sp[BPW][2][Q], cp[BPW][2][Q];
+    __shared__ double sj[BPW][2][2][Q], cj[BPW][2][2][Q];
+    __shared__ double r0c[BPW][2], ct0[BPW][2], st0[BPW][2];
 
     const int tid = threadIdx.x;
+    const int bbl = tid / TPB, rr = tid - bbl * TPB;
+    const size_t blk = (size_t)blockIdx.x * BPW + bbl;
+    const bool active = bbl < BPW && blk < nblk;
     const int lB = g.L - level;
-    const size_t blk = blockIdx.x;
-    const uint32_t mB = (uint32_t)(blk & (((size_t)1 << (2 * lB)) - 1));
-    const uint32_t mAp = (uint32_t)(blk >> (2 * lB));
-    int b1, b2, ap1, ap2;
-    morton_decode(mB, b1, b2);
-    morton_decode(mAp, ap1, ap2);
-    const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
     const size_t nBl = (size_t)1 << (2 * lB);
+    const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
 
     const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) Ms[i] = Mg[i];
-    for (int i = tid; i < 4 * QQ; i += NT) acc4[i] = {(T)0, (T)0};
-    if (tid < 2) {
-        r0c[tid] = g.rho_scale * box_centre(2 * b1 + tid, lB + 1);
-        double s_, c_;
-        sincospi(2.0 * box_centre(2 * b2 + tid, lB + 1), &s_, &c_);
-        ct0[tid] = c_;
-        st0[tid] = s_;
-    }
-    for (int j = 0; j < 4; ++j) {
-        const int j1 = j >> 1, j2 = j & 1;
-        const uint32_t mA = 4 * mAp + j;
-        const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
-        if (tid >= 64 && tid < 64 + Q) {
-            const int t = tid - 64;
+    for (int i = tid; i < 2 * QQ; i += NT) (&Ms[0][0][0])[i] = Mg[i];
+    uint32_t mB = 0, mAp = 0;
+    int b1 = 0, b2 = 0, ap1 = 0, ap2 = 0;
+    if (active) {
+        mB = (uint32_t)(blk & (nBl - 1));
+        mAp = (uint32_t)(blk >> (2 * lB));
+        morton_decode(mB, b1, b2);
+        morton_decode(mAp, ap1, ap2);
+        if (rr < 2 * Q) {
+            const int d = rr / Q, t = rr - d * Q;
             double s_ = 0, c_ = 1;
-            if (ell) sincospi(2.0 * box_node(a1, level, tb.z[t]), &s_, &c_);
-            sx1[t] = s_;
-            cx1[t] = c_;
-        } else if (tid >= 128 && tid < 128 + Q) {
-            const int t = tid - 128;
+            if (ell) sincospi(2.0 * box_node(d ? ap2 : ap1, level - 1, tb.z[t]), &s_, &c_);
+            sp[bbl][d][t] = s_;
+            cp[bbl][d][t] = c_;
+        } else if (rr < 6 * Q) {
+            const int k = rr - 2 * Q, d = k / (2 * Q), a = (k / Q) & 1, t = k % Q;
             double s_ = 0, c_ = 1;
-            if (ell) sincospi(2.0 * box_node(a2, level, tb.z[t]), &s_, &c_);
-            sx2[t] = s_;
-            cx2[t] = c_;
+            if (ell) sincospi(2.0 * box_node(2 * (d ? ap2 : ap1) + a, level, tb.z[t]), &s_, &c_);
+            sj[bbl][d][a][t] = s_;
+            cj[bbl][d][a][t] = c_;
+        } else if (rr < 6 * Q + 2) {
+            const int c = rr - 6 * Q;
+            r0c[bbl][c] = g.rho_scale * box_centre(2 * b1 + c, lB + 1);
+            double s_, c_;
+            sincospi(2.0 * box_centre(2 * b2 + c, lB + 1), &s_, &c_);
+            ct0[bbl][c] = c_;
+            st0[bbl][c] = s_;
         }
-        __syncthreads();
-        // v[c][t] = conj E(x^{A_j}_t, p0(B_c)) delta^{A_j B}_t
-        const cpx<T> *src = win + ((size_t)mA * nBl + mB) * QQ;
-        for (int i = tid; i < QQ; i += NT) {
-            const int t1 = i / Q, t2 = i - t1 * Q;
-            const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[t2]),
-                                     sx1[t1], cx1[t1], sx2[t2], cx2[t2]);
-            const double G0 = phase_dir(xp, ct0[0], st0[0]);
-            const double G1 = phase_dir(xp, ct0[1], st0[1]);
-            const cpx<T> d = src[i];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) v[c * QQ + i] = cmulc(d, cis<T>(r0c[c >> 1] * ((c & 1) ? G1 : G0)));
-        }
-        __syncthreads();
-        // Y[c][t1][t'2] = sum_t2 M_j2[t'2][t2] v[c][t1][t2]
-        for (int i = tid; i < 4 * QQ; i += NT) {
-            const int c = i / QQ, r = i - c * QQ;
-            const int t1 = r / Q, tp2 = r - t1 * Q;
-            const cpx<T> *vv = v + c * QQ + t1 * Q;
-            const T *mm = Ms + j2 * QQ + tp2 * Q;
-            cpx<T> a = {(T)0, (T)0};
-#pragma unroll
-            for (int t2 = 0; t2 < Q; ++t2) crfma(a, mm[t2], vv[t2]);
-            Y[i] = a;
-        }
-        __syncthreads();
-        // acc4[c][t'1][t'2] += sum_t1 M_j1[t'1][t1] Y[c][t1][t'2]
-        for (int i = tid; i < 4 * QQ; i += NT) {
-            const int c = i / QQ, r = i - c * QQ;
-            const int tp1 = r / Q, tp2 = r - tp1 * Q;
-            const T *mm = Ms + j1 * QQ + tp1 * Q;
-            cpx<T> a = acc4[i];
-#pragma unroll
-            for (int t1 = 0; t1 < Q; ++t1) crfma(a, mm[t1], Y[c * QQ + t1 * Q + tp2]);
-            acc4[i] = a;
-        }
-        __syncthreads();
-    }
-    // sin/cos tables of A_p's nodes, then the factor E(x^{A_p}_t', p0(B_c))
-    if (tid < Q) {
-        double s_ = 0, c_ = 1;
-        if (ell) sincospi(2.0 * box_node(ap1, level - 1, tb.z[tid]), &s_, &c_);
-        sx1[tid] = s_;
-        cx1[tid] = c_;
-    } else if (tid >= 64 && tid < 64 + Q) {
-        const int t = tid - 64;
-        double s_ = 0, c_ = 1;
-        if (ell) sincospi(2.0 * box_node(ap2, level - 1, tb.z[t]), &s_, &c_);
-        sx2[t] = s_;
-        cx2[t] = c_;
     }
     __syncthreads();
-    cpx<T> *dst = wout + blk * (4 * QQ);
-    for (int i = tid; i < 2 * QQ; i += NT) {
-        const int c2 = i / QQ, tp = i - c2 * QQ;
-        const int tp1 = tp / Q, tp2 = tp - tp1 * Q;
-        const XP xp = make_xp_sc(ph, box_node(ap1, level - 1, tb.z[tp1]), box_node(ap2, level - 1, tb.z[tp2]),
-                                 sx1[tp1], cx1[tp1], sx2[tp2], cx2[tp2]);
-        const double G = phase_dir(xp, ct0[c2], st0[c2]);
+    {
+        // rr = ((j1 * 2 + c2) * Q + t1) * 2 + j2: the two j2 of a row are adjacent lanes
+        const int j2 = rr & 1, k = rr >> 1;
+        const int t1 = k % Q, jc = k / Q, c2 = jc & 1, j1 = jc >> 1;
+        cpx<T> acc0[Q], acc1[Q];   // c1 = 0, 1
 #pragma unroll
-        for (int c1 = 0; c1 < 2; ++c1) {
-            const int c = 2 * c1 + c2;
-            dst[c * QQ + tp] = cmul(acc4[c * QQ + tp], cis<T>(r0c[c1] * G));
+        for (int t = 0; t < Q; ++t) acc0[t] = acc1[t] = {(T)0, (T)0};
+        if (active) {
+            const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
+            const cpx<T> *src = win + ((size_t)(4 * mAp + 2 * j1 + j2) * nBl + mB) * QQ + t1 * Q;
+            const double xa1 = box_node(a1, level, tb.z[t1]);
+#pragma unroll
+            for (int t2 = 0; t2 < Q; ++t2) {
+                const XP xp = make_xp_sc(ph, xa1, box_node(a2, level, tb.z[t2]), sj[bbl][0][j1][t1],
+                                         cj[bbl][0][j1][t1], sj[bbl][1][j2][t2], cj[bbl][1][j2][t2]);
+                const double G = phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]);
+                const cpx<T> d = src[t2];
+                const cpx<T> v0 = cmulc(d, cis<T>(r0c[bbl][0] * G));
+                const cpx<T> v1 = cmulc(d, cis<T>(r0c[bbl][1] * G));
+#pragma unroll
+                for (int tp2 = 0; tp2 < Q; ++tp2) {
+                    const T m = Ms[j2][tp2][t2];
+                    crfma(acc0[tp2], m, v0);
+                    crfma(acc1[tp2], m, v1);
+                }
+            }
+        }
+        // add the partner lane's (other j2) partial rows
+#pragma unroll
+        for (int t = 0; t < Q; ++t) {
+            acc0[t].re += __shfl_xor(acc0[t].re, 1);
+            acc0[t].im += __shfl_xor(acc0[t].im, 1);
+            acc1[t].re += __shfl_xor(acc1[t].re, 1);
+            acc1[t].im += __shfl_xor(acc1[t].im, 1);
+        }
+        if (active && j2 == 0) {
+#pragma unroll
+            for (int tp2 = 0; tp2 < Q; ++tp2) {
+                Y[bbl][j1][c2][t1 * Q + tp2] = acc0[tp2];        // c = 2*0 + c2
+                Y[bbl][j1][2 + c2][t1 * Q + tp2] = acc1[tp2];    // c = 2*1 + c2
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+        // second pass: thread (c, t'2, half)
+        const int c = rr / (2 * Q), k = rr - c * 2 * Q;
+        const int h = k / Q, tp2 = k - h * Q;
+        const int c1 = c >> 1, c2 = c & 1;
+        cpx<T> acc[H1];
+#pragma unroll
+        for (int kk = 0; kk < H1; ++kk) acc[kk] = {(T)0, (T)0};
+#pragma unroll
+        for (int j1 = 0; j1 < 2; ++j1) {
+            cpx<T> col[Q];
+#pragma unroll
+            for (int t1 = 0; t1 < Q; ++t1) col[t1] = Y[bbl][j1][c][t1 * Q + tp2];
+#pragma unroll
+            for (int kk = 0; kk < H1; ++kk) {
+                const int tp1 = min(h * H1 + kk, Q - 1);
+#pragma unroll
+                for (int t1 = 0; t1 < Q; ++t1) crfma(acc[kk], Ms[j1][tp1][t1], col[t1]);
+            }
+        }
+        cpx<T> *dst = wout + (blk * 4 + c) * QQ;
+        const double xa2 = box_node(ap2, level - 1, tb.z[tp2]);
+#pragma unroll
+        for (int kk = 0; kk < H1; ++kk) {
+            const int tp1 = h * H1 + kk;
+            if (tp1 < Q) {
+                const XP xp = make_xp_sc(ph, box_node(ap1, level - 1, tb.z[tp1]), xa2, sp[bbl][0][tp1],
+                                         cp[bbl][0][tp1], sp[bbl][1][tp2], cp[bbl][1][tp2]);
+                const double G = phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]);
+                dst[tp1 * Q + tp2] = cmul(acc[kk], cis<T>(r0c[bbl][c1] * G));
+            }
         }
     }
 }
@@ -859,93 +924,117 @@ __global__ __launch_bounds__(NT) void k_switch_adj(Geom g, PhaseDev ph, Tables t
 // p-level^H at level l: from the outputs (A_j, B) back to the inputs (A_p, B_c)
 //   delta^{A_p B_c}_t' = sum_j conj E(x0(A_j), p^{B_c}_t') sum_t M_c1[t1][t'1] M_c2[t2][t'2]
 //                          E(x0(A_j), p^B_t) delta^{A_j B}_t
+// First pass: thread (j, c2, t1) forms row t1 of E delta for output j and
+// contracts it over t2 with M_c2.  Second pass: thread (c, t'2, half)
+// contracts over t1 with M_c1, applies conj E(x0(A_j), p^{B_c}_t') and sums j.
 template <typename T, int Q>
 __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables tb, int level,
                                                    const cpx<T> *__restrict__ win,
-                                                   cpx<T> *__restrict__ wout) {
+                                                   cpx<T> *__restrict__ wout, unsigned nblk) {
     constexpr int QQ = Q * Q;
-    __shared__ cpx<T> gj[QQ];
-    __shared__ cpx<T> Y[2 * QQ];
-    __shared__ cpx<T> acc4[4 * QQ];
-    __shared__ T Ms[2 * QQ];
-    __shared__ double rc[2 * Q], ctc[2 * Q], stc[2 * Q];
-    __shared__ double rb[Q], ctb[Q], stb[Q];
-    __shared__ double Gc[2 * Q], Gb[Q];
+    constexpr int TPO = 2 * Q;
+    constexpr int TPB = 4 * TPO;
+    constexpr int BPW = blocks_per_wg<T, Q, 8>();
+    constexpr int H1 = (Q + 1) / 2;
+    __shared__ T Ms[2][Q][Q];             // Ms[c][t][t'] = M_c[t][t']
+    __shared__ double rc[BPW][2 * Q], ctc[BPW][2 * Q], stc[BPW][2 * Q];
+    __shared__ double rb[BPW][Q], ctb[BPW][Q], stb[BPW][Q];
+    __shared__ double Gc[BPW][4][2 * Q], Gb[BPW][4][Q];
+    __shared__ cpx<T> Y[BPW][4][2][QQ];   // [j][c2][t1][t'2]
 
     const int tid = threadIdx.x;
+    const int bbl = tid / TPB, r = tid - bbl * TPB;
+    const int j = r / TPO, rr = r - j * TPO;
+    const size_t blk = (size_t)blockIdx.x * BPW + bbl;
+    const bool active = bbl < BPW && blk < nblk;
     const int lB = g.L - level;
-    const size_t blk = blockIdx.x;
-    const uint32_t mB = (uint32_t)(blk & (((size_t)1 << (2 * lB)) - 1));
-    const uint32_t mAp = (uint32_t)(blk >> (2 * lB));
-    int b1, b2, ap1, ap2;
-    morton_decode(mB, b1, b2);
-    morton_decode(mAp, ap1, ap2);
     const size_t nBl = (size_t)1 << (2 * lB);
 
     const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) Ms[i] = Mg[i];
-    for (int i = tid; i < 4 * QQ; i += NT) acc4[i] = {(T)0, (T)0};
-    if (tid < 2 * Q) {
-        const int c = tid / Q, t = tid - c * Q;
-        const double z = tb.z[t];
-        rc[tid] = g.rho_scale * box_node(2 * b1 + c, lB + 1, z);
-        double s_, c_;
-        sincospi(2.0 * box_node(2 * b2 + c, lB + 1, z), &s_, &c_);
-        ctc[tid] = c_;
-        stc[tid] = s_;
-    } else if (tid >= 64 && tid < 64 + Q) {
-        const int t = tid - 64;
-        const double z = tb.z[t];
-        rb[t] = g.rho_scale * box_node(b1, lB, z);
-        double s_, c_;
-        sincospi(2.0 * box_node(b2, lB, z), &s_, &c_);
-        ctb[t] = c_;
-        stb[t] = s_;
+    for (int i = tid; i < 2 * QQ; i += NT) (&Ms[0][0][0])[i] = Mg[i];
+    uint32_t mB = 0, mAp = 0;
+    int b1 = 0, b2 = 0, ap1 = 0, ap2 = 0;
+    if (active) {
+        mB = (uint32_t)(blk & (nBl - 1));
+        mAp = (uint32_t)(blk >> (2 * lB));
+        morton_decode(mB, b1, b2);
+        morton_decode(mAp, ap1, ap2);
+        if (j == 0) {
+            const int c = rr / Q, t = rr - c * Q;
+            const double z = tb.z[t];
+            rc[bbl][rr] = g.rho_scale * box_node(2 * b1 + c, lB + 1, z);
+            double s_, c_;
+            sincospi(2.0 * box_node(2 * b2 + c, lB + 1, z), &s_, &c_);
+            ctc[bbl][rr] = c_;
+            stc[bbl][rr] = s_;
+        } else if (j == 1 && rr < Q) {
+            const double z = tb.z[rr];
+            rb[bbl][rr] = g.rho_scale * box_node(b1, lB, z);
+            double s_, c_;
+            sincospi(2.0 * box_node(b2, lB, z), &s_, &c_);
+            ctb[bbl][rr] = c_;
+            stb[bbl][rr] = s_;
+        }
     }
     __syncthreads();
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t mA = 4 * mAp + j;
+    if (active) {
         const int a1 = 2 * ap1 + (j >> 1), a2 = 2 * ap2 + (j & 1);
         const XP xp = make_xp(ph, box_centre(a1, level), box_centre(a2, level));
-        if (tid < 2 * Q) Gc[tid] = phase_dir(xp, ctc[tid], stc[tid]);
-        else if (tid >= 64 && tid < 64 + Q) Gb[tid - 64] = phase_dir(xp, ctb[tid - 64], stb[tid - 64]);
-        __syncthreads();
-        const cpx<T> *src = win + ((size_t)mA * nBl + mB) * QQ;
-        for (int i = tid; i < QQ; i += NT) {
-            const int t1 = i / Q, t2 = i - t1 * Q;
-            gj[i] = cmul(src[i], cis<T>(rb[t1] * Gb[t2]));
-        }
-        __syncthreads();
-        // Y[c1][t1][t'2]... first the second dimension: Y[c2][t1][t'2] = sum_t2 M_c2[t2][t'2] g[t1][t2]
-        for (int i = tid; i < 2 * QQ; i += NT) {
-            const int c2 = i / QQ, r = i - c2 * QQ;
-            const int t1 = r / Q, tp2 = r - t1 * Q;
-            const T *mm = Ms + c2 * QQ + tp2;
-            const cpx<T> *gg = gj + t1 * Q;
-            cpx<T> a = {(T)0, (T)0};
-#pragma unroll
-            for (int t2 = 0; t2 < Q; ++t2) crfma(a, mm[t2 * Q], gg[t2]);
-            Y[i] = a;
-        }
-        __syncthreads();
-        // then the first dimension and the conj prefactor, accumulated over j
-        for (int i = tid; i < 4 * QQ; i += NT) {
-            const int c = i / QQ, r = i - c * QQ;
-            const int c1 = c >> 1, c2 = c & 1;
-            const int tp1 = r / Q, tp2 = r - tp1 * Q;
-            const T *mm = Ms + c1 * QQ + tp1;
-            cpx<T> a = {(T)0, (T)0};
-#pragma unroll
-            for (int t1 = 0; t1 < Q; ++t1) crfma(a, mm[t1 * Q], Y[c2 * QQ + t1 * Q + tp2]);
-            const cpx<T> e = cis<T>(rc[c1 * Q + tp1] * Gc[c2 * Q + tp2]);
-            const cpx<T> add = cmulc(a, e);
-            acc4[i].re += add.re;
-            acc4[i].im += add.im;
-        }
-        __syncthreads();
+        Gc[bbl][j][rr] = phase_dir(xp, ctc[bbl][rr], stc[bbl][rr]);
+        if (rr < Q) Gb[bbl][j][rr] = phase_dir(xp, ctb[bbl][rr], stb[bbl][rr]);
     }
-    cpx<T> *dst = wout + blk * (4 * QQ);
-    for (int i = tid; i < 4 * QQ; i += NT) dst[i] = acc4[i];
+    __syncthreads();
+    if (active) {
+        // first pass: thread (j, c2, t1)
+        const int c2 = rr / Q, t1 = rr - c2 * Q;
+        const cpx<T> *src = win + ((size_t)(4 * mAp + j) * nBl + mB) * QQ + t1 * Q;
+        const double rho = rb[bbl][t1];
+        cpx<T> acc[Q];
+#pragma unroll
+        for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
+#pragma unroll
+        for (int t2 = 0; t2 < Q; ++t2) {
+            const cpx<T> gv = cmul(src[t2], cis<T>(rho * Gb[bbl][j][t2]));
+#pragma unroll
+            for (int tp2 = 0; tp2 < Q; ++tp2) crfma(acc[tp2], Ms[c2][t2][tp2], gv);
+        }
+#pragma unroll
+        for (int tp2 = 0; tp2 < Q; ++tp2) Y[bbl][j][c2][t1 * Q + tp2] = acc[tp2];
+    }
+    __syncthreads();
+    if (active) {
+        // second pass: thread (c, t'2, half); r = c * 2Q + h * Q + t'2
+        const int c = r / (2 * Q), k = r - c * 2 * Q;
+        const int h = k / Q, tp2 = k - h * Q;
+        const int c1 = c >> 1, c2 = c & 1;
+        cpx<T> acc[H1];
+#pragma unroll
+        for (int kk = 0; kk < H1; ++kk) acc[kk] = {(T)0, (T)0};
+#pragma unroll 1
+        for (int jj = 0; jj < 4; ++jj) {
+            cpx<T> col[Q];
+#pragma unroll
+            for (int t1 = 0; t1 < Q; ++t1) col[t1] = Y[bbl][jj][c2][t1 * Q + tp2];
+            const double G = Gc[bbl][jj][c2 * Q + tp2];
+#pragma unroll
+            for (int kk = 0; kk < H1; ++kk) {
+                const int tp1 = min(h * H1 + kk, Q - 1);
+                cpx<T> z = {(T)0, (T)0};
+#pragma unroll
+                for (int t1 = 0; t1 < Q; ++t1) crfma(z, Ms[c1][t1][tp1], col[t1]);
+                const cpx<T> e = cis<T>(rc[bbl][c1 * Q + tp1] * G);
+                const cpx<T> add = cmulc(z, e);
+                acc[kk].re += add.re;
+                acc[kk].im += add.im;
+            }
+        }
+        cpx<T> *dst = wout + (blk * 4 + c) * QQ;
+#pragma unroll
+        for (int kk = 0; kk < H1; ++kk) {
+            const int tp1 = h * H1 + kk;
+            if (tp1 < Q) dst[tp1 * Q + tp2] = acc[kk];
+        }
+    }
 }
 
 // initialisation^H: f(p) = sum_A conj E(x0(A), p) sum_t L^B_t(p) E(x0(A), p^B_t) delta^{AB}_t
@@ -1073,8 +1162,11 @@ static hipError_t plevel_t(const Geom &g, const PhaseDev &ph, const Tables &tb, 
                            const void *win, void *wout, hipStream_t st) {
     const unsigned nblk = 1u << (2 * g.L - 2);
 #define L_PL(Q)                                                                                      \
-    hipLaunchKernelGGL((k_plevel<T, Q>), dim3(nblk), dim3(NT), 0, st, g, ph, tb, level,              \
-                       (const cpx<T> *)win, (cpx<T> *)wout);
+    {                                                                                                \
+        constexpr int BPW = blocks_per_wg<T, Q, 8>();                                                \
+        hipLaunchKernelGGL((k_plevel<T, Q>), dim3((nblk + BPW - 1) / BPW), dim3(NT), 0, st, g, ph,   \
+                           tb, level, (const cpx<T> *)win, (cpx<T> *)wout, nblk);                    \
+    }
     FIO_DISPATCH_Q(g.q, L_PL)
 #undef L_PL
     return hipGetLastError();
@@ -1085,8 +1177,11 @@ static hipError_t xlevel_t(const Geom &g, const PhaseDev &ph, const Tables &tb, 
                            const void *win, void *wout, hipStream_t st) {
     const unsigned nblk = 1u << (2 * g.L - 2);
 #define L_XL(Q)                                                                                      \
-    hipLaunchKernelGGL((k_xlevel<T, Q>), dim3(nblk), dim3(NT), 0, st, g, ph, tb, level,              \
-                       (const cpx<T> *)win, (cpx<T> *)wout);
+    {                                                                                                \
+        constexpr int BPW = blocks_per_wg<T, Q, 12>();                                               \
+        hipLaunchKernelGGL((k_xlevel<T, Q>), dim3((nblk + BPW - 1) / BPW), dim3(NT), 0, st, g, ph,   \
+                           tb, level, (const cpx<T> *)win, (cpx<T> *)wout, nblk);                    \
+    }
     FIO_DISPATCH_Q(g.q, L_XL)
 #undef L_XL
     return hipGetLastError();
@@ -1135,8 +1230,11 @@ static hipError_t xlevel_adj_t(const Geom &g, const PhaseDev &ph, const Tables &
                                const void *win, void *wout, hipStream_t st) {
     const unsigned nblk = 1u << (2 * g.L - 2);
 #define L_XLA(Q)                                                                                     \
-    hipLaunchKernelGGL((k_xlevel_adj<T, Q>), dim3(nblk), dim3(NT), 0, st, g, ph, tb, level,          \
-                       (const cpx<T> *)win, (cpx<T> *)wout);
+    {                                                                                                \
+        constexpr int BPW = blocks_per_wg<T, Q, 8>();                                                \
+        hipLaunchKernelGGL((k_xlevel_adj<T, Q>), dim3((nblk + BPW - 1) / BPW), dim3(NT), 0, st, g,   \
+                           ph, tb, level, (const cpx<T> *)win, (cpx<T> *)wout, nblk);                \
+    }
     FIO_DISPATCH_Q(g.q, L_XLA)
 #undef L_XLA
     return hipGetLastError();
@@ -1163,8 +1261,11 @@ static hipError_t plevel_adj_t(const Geom &g, const PhaseDev &ph, const Tables &
                                const void *win, void *wout, hipStream_t st) {
     const unsigned nblk = 1u << (2 * g.L - 2);
 #define L_PLA(Q)                                                                                     \
-    hipLaunchKernelGGL((k_plevel_adj<T, Q>), dim3(nblk), dim3(NT), 0, st, g, ph, tb, level,          \
-                       (const cpx<T> *)win, (cpx<T> *)wout);
+    {                                                                                                \
+        constexpr int BPW = blocks_per_wg<T, Q, 8>();                                                \
+        hipLaunchKernelGGL((k_plevel_adj<T, Q>), dim3((nblk + BPW - 1) / BPW), dim3(NT), 0, st, g,   \
+                           ph, tb, level, (const cpx<T> *)win, (cpx<T> *)wout, nblk);                \
+    }
     FIO_DISPATCH_Q(g.q, L_PLA)
 #undef L_PLA
     return hipGetLastError();
