@@ -74,7 +74,7 @@ def main():
 
     torch.cuda.set_device(0)
     N, q, R = args.N, args.q, args.nrhs
-    plan = fio.Plan(N, q, fio.Phase(), dtype=torch.complex64)
+    plan = fio.Plan(N, q, fio.Phase(), dtype=torch.complex64, nrhs_max=R)
     f_host = white_noise(N, 3, nrhs=R)
     f = torch.as_tensor(f_host).to(torch.complex64).cuda()
     u = torch.empty_like(f)

@@ -87,8 +87,12 @@ typedef struct {
     int lm;       /* switch level (eq:alg2m); default floor(L/2); must satisfy
                      s <= lm <= L - s                                          */
     int dtype;    /* FIO_C64 (default) or FIO_C128                             */
-    int nrhs_max; /* reserved: the largest nrhs a batched apply will use
-                     (default 1); the plain path needs no per-RHS workspace    */
+    int nrhs_max; /* right-hand sides processed together (default 1, at most
+                     4096): the plan holds two weight buffers of nrhs_max
+                     N^2 q^2 complex values, and fio_apply / fio_apply_adjoint
+                     take nrhs in chunks of nrhs_max, computing every kernel
+                     value of the levels and the switch once per chunk (the
+                     vectorised butterfly of Sec. 4, last paragraphs)        */
 } fio_plan_opts_t;
 
 /* Geometry and sizes of a plan. */
@@ -98,6 +102,7 @@ typedef struct {
     int64_t weights_per_level;/* complex weights per level per RHS = N^2 q^2      */
     int64_t workspace_bytes;  /* device memory owned by the plan                  */
     int max_box_sources;      /* largest number of sources in a level-(L-s) box */
+    int nrhs_max;             /* right-hand sides per chunk                        */
 } fio_plan_info_t;
 
 /* Create a plan for an N x N problem with q Chebyshev points per dimension
@@ -109,9 +114,9 @@ typedef struct {
  * Builds T_P for the polar images of Omega (Sec. 4 step 1; sources sorted by
  * their level-(L-s) box) and the interpolation tables (the Lagrange values
  * L^B_t(p^{B_c}_t') are the same for every pair and level, Sec. 4), and
- * allocates two weight buffers of N^2 q^2 complex values each (only two
- * consecutive levels of weights are ever live, Sec. 4) on the current
- * device.  Returns FIO_OK, FIO_EINVAL, FIO_ENOMEM or FIO_EDEVICE. */
+ * allocates two weight buffers of nrhs_max x N^2 q^2 complex values each
+ * (only two consecutive levels of weights are ever live, Sec. 4) on the
+ * current device.  Returns FIO_OK, FIO_EINVAL, FIO_ENOMEM or FIO_EDEVICE. */
 int fio_plan(int N, int q, const fio_phase_t *phase, fio_plan_t *out);
 int fio_plan_ex(int N, int q, const fio_phase_t *phase,
                 const fio_plan_opts_t *opts, fio_plan_t *out);
@@ -127,7 +132,9 @@ int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info);
  *      Read only.
  *   u: device, nrhs x N x N complex (plan dtype), u[r][i1][i2] = u_r(i1/N,
  *      i2/N).  Fully overwritten.  Must not overlap f.
- *   nrhs >= 1 right-hand sides, processed one after another.
+ *   nrhs >= 1 right-hand sides, processed in chunks of the plan's nrhs_max;
+ *   within a chunk the kernel values of the levels and the switch are
+ *   computed once and applied to every right-hand side.
  * Asynchronous on `stream`; FIO_EINVAL before any launch on bad arguments. */
 int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream);
 

@@ -77,7 +77,7 @@ class _CInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("q", ctypes.c_int), ("L", ctypes.c_int), ("s", ctypes.c_int),
                 ("lm", ctypes.c_int), ("dtype", ctypes.c_int), ("n_pairs", ctypes.c_int64),
                 ("weights_per_level", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
-                ("max_box_sources", ctypes.c_int)]
+                ("max_box_sources", ctypes.c_int), ("nrhs_max", ctypes.c_int)]
 
 
 _lib = None
@@ -127,18 +127,20 @@ class Plan:
     N: grid side (power of two, 8..8192); q: Chebyshev points per dimension
     (3..16); phase: :class:`Phase`; s, lm: start offset and switch level
     (defaults min(3, L/2) and L/2); dtype: torch.complex64 (FP32 weights,
-    FP64 phases) or torch.complex128 (FP64 throughout).
+    FP64 phases) or torch.complex128 (FP64 throughout); nrhs_max: right-hand
+    sides processed together, sharing every kernel value of the levels and
+    the switch (the plan holds 2 x nrhs_max x N^2 q^2 complex weights).
     """
 
     def __init__(self, N: int, q: int, phase: Phase = Phase(), s: int | None = None,
-                 lm: int | None = None, dtype: torch.dtype = torch.complex64):
+                 lm: int | None = None, dtype: torch.dtype = torch.complex64, nrhs_max: int = 1):
         lib = load_library()
         if dtype not in (torch.complex64, torch.complex128):
             raise ValueError("dtype must be torch.complex64 or torch.complex128")
         self.dtype = dtype
         self.device = torch.device("cuda", torch.cuda.current_device())
         opts = _COpts(-1 if s is None else int(s), -1 if lm is None else int(lm),
-                      C64 if dtype == torch.complex64 else C128, -1)
+                      C64 if dtype == torch.complex64 else C128, int(nrhs_max))
         h = ctypes.c_void_p()
         _check(lib.fio_plan_ex(int(N), int(q), ctypes.byref(_cphase(phase)), ctypes.byref(opts),
                                ctypes.byref(h)), "fio_plan_ex")
@@ -149,6 +151,7 @@ class Plan:
         self.N, self.q, self.L, self.s, self.lm = info.N, info.q, info.L, info.s, info.lm
         self.workspace_bytes = int(info.workspace_bytes)
         self.max_box_sources = int(info.max_box_sources)
+        self.nrhs_max = int(info.nrhs_max)
         self.n_stages = self.L - 2 * self.s + 2
 
     # -- lifetime ---------------------------------------------------------

@@ -1,5 +1,5 @@
 // Internal definitions shared by the host plan (fio_plan.cpp) and the HIP
-// kernels (fio_kernels.hip).  Not part of the public ABI.
+// kernels (fio_kernels_fwd.hip, fio_kernels_adj.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,16 +50,18 @@ struct Sources {
     const int32_t *off;     // off[mB] .. off[mB+1]: sources of the box with Morton index mB
 };
 
-// Kernel launchers (defined in fio_kernels.hip).  All return hipError_t of the launch.
-// `dtype` selects FP64 (FIO_C128) or FP32 (FIO_C64) weights.
+// Kernel launchers (defined in fio_kernels_fwd.hip / fio_kernels_adj.hip).  All return hipError_t of the launch.
+// `dtype` selects FP64 (FIO_C128) or FP32 (FIO_C64) weights.  The level and
+// switch launchers process `nrhs` right-hand sides whose weights are planes
+// `plane` complex values apart; initialisation and termination take one.
 hipError_t launch_init(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
                        const Sources &src, const void *f, void *w_out, hipStream_t st);
 hipError_t launch_plevel(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
-                         const void *w_in, void *w_out, hipStream_t st);
+                         const void *w_in, void *w_out, int nrhs, size_t plane, hipStream_t st);
 hipError_t launch_switch(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
-                         void *w, hipStream_t st);
+                         void *w, int nrhs, size_t plane, hipStream_t st);
 hipError_t launch_xlevel(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
-                         const void *w_in, void *w_out, hipStream_t st);
+                         const void *w_in, void *w_out, int nrhs, size_t plane, hipStream_t st);
 hipError_t launch_term(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
                        const void *w_in, void *u, hipStream_t st);
 
@@ -67,11 +69,11 @@ hipError_t launch_term(int dtype, const Geom &g, const PhaseDev &ph, const Table
 hipError_t launch_term_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
                            const void *u, void *w_out, hipStream_t st);
 hipError_t launch_xlevel_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
-                             const void *w_in, void *w_out, hipStream_t st);
+                             const void *w_in, void *w_out, int nrhs, size_t plane, hipStream_t st);
 hipError_t launch_switch_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
-                             void *w, hipStream_t st);
+                             void *w, int nrhs, size_t plane, hipStream_t st);
 hipError_t launch_plevel_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
-                             const void *w_in, void *w_out, hipStream_t st);
+                             const void *w_in, void *w_out, int nrhs, size_t plane, hipStream_t st);
 hipError_t launch_init_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
                            const Sources &src, const void *w_in, void *f, hipStream_t st);
 

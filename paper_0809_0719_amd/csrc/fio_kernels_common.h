@@ -1,0 +1,109 @@
+// Shared device helpers and launch-shape constants of the butterfly kernels
+// (forward kernels in fio_kernels_fwd.hip, adjoints in fio_kernels_adj.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fio_device.h"
+
+namespace fio {
+
+constexpr int NT = 256;  // threads per workgroup for every kernel here
+
+// ---------------------------------------------------------------------------
+// Shared helpers
+// ---------------------------------------------------------------------------
+
+// Lagrange basis values L_t(u), t < Q, on the Chebyshev grid z (barycentric
+// form of the second kind, with lam the barycentric weights).
+template <typename T, int Q>
+__device__ __forceinline__ void lagrange_row(double u, const double *z, const double *lam, T *out) {
+    int exact = -1;
+    double ssum = 0.0;
+    double tmp[Q];
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+        const double d = u - z[t];
+        if (d == 0.0) exact = t;
+        tmp[t] = lam[t] / d;
+        ssum += tmp[t];
+    }
+    if (exact >= 0) {
+#pragma unroll
+        for (int t = 0; t < Q; ++t) out[t] = (T)(t == exact ? 1.0 : 0.0);
+    } else {
+        const double inv = 1.0 / ssum;
+#pragma unroll
+        for (int t = 0; t < Q; ++t) out[t] = (T)(tmp[t] * inv);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ const T *pick_M(const Tables &tb);
+template <>
+__device__ __forceinline__ const float *pick_M<float>(const Tables &tb) { return tb.Mf; }
+template <>
+__device__ __forceinline__ const double *pick_M<double>(const Tables &tb) { return tb.M; }
+
+template <typename T>
+__device__ __forceinline__ const T *pick_T(const Tables &tb);
+template <>
+__device__ __forceinline__ const float *pick_T<float>(const Tables &tb) { return tb.Ttf; }
+template <>
+__device__ __forceinline__ const double *pick_T<double>(const Tables &tb) { return tb.Tt; }
+
+// ===========================================================================
+// Butterfly blocks per workgroup for the level kernels: 8q threads per block
+// (2q per output pair), limited so the block's LDS stays near 40 KB.
+// ===========================================================================
+template <typename T, int Q, int PERBB>
+constexpr int blocks_per_wg() {
+    constexpr int byT = NT / (8 * Q);
+    constexpr int byL = 40960 / (PERBB * Q * Q * (int)sizeof(cpx<T>));
+    constexpr int b = byT < byL ? byT : byL;
+    return b < 1 ? 1 : b;
+}
+
+// B boxes per chunk: keeps the chunk's weights and partial sums within 32 KB of LDS.
+template <typename T, int Q>
+constexpr int bch() {
+    return (32768 / (Q * Q * 2 * (int)sizeof(T))) < 16 ? (32768 / (Q * Q * 2 * (int)sizeof(T))) : 16;
+}
+
+// right-hand sides per chunk of the switch kernels
+template <typename T>
+constexpr int switch_rc() { return sizeof(T) == 4 ? 8 : 4; }
+
+template <typename T>
+constexpr int swadj_rc() { return sizeof(T) == 4 ? 2 : 1; }
+
+template <typename T, int Q, int RC>
+constexpr int swadj_ppb() {
+    constexpr int byL = 32768 / (Q * Q * RC * (int)sizeof(cpx<T>));
+    return byL < (NT / Q) ? byL : (NT / Q);
+}
+
+
+#define FIO_DISPATCH_Q(q, MACRO) \
+    switch (q) {                 \
+        case 3: MACRO(3); break; \
+        case 4: MACRO(4); break; \
+        case 5: MACRO(5); break; \
+        case 6: MACRO(6); break; \
+        case 7: MACRO(7); break; \
+        case 8: MACRO(8); break; \
+        case 9: MACRO(9); break; \
+        case 10: MACRO(10); break; \
+        case 11: MACRO(11); break; \
+        case 12: MACRO(12); break; \
+        case 13: MACRO(13); break; \
+        case 14: MACRO(14); break; \
+        case 15: MACRO(15); break; \
+        case 16: MACRO(16); break; \
+        default: return hipErrorInvalidValue; \
+    }
+
+#define FIO_BY_DTYPE(dtype, CALL) \
+    ((dtype) == FIO_C128 ? CALL(double) : CALL(float))
+
+}  // namespace fio

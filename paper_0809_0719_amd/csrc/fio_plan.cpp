@@ -1,6 +1,6 @@
 // Host side of the C ABI: argument validation, the plan (trees of Sec. 4
 // step 1, interpolation tables, workspace), and the level schedule that
-// drives the kernels of fio_kernels.hip.
+// drives the kernels of fio_kernels_fwd.hip and fio_kernels_adj.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -82,10 +82,11 @@ double lagrange(const std::vector<double> &z, int t, double u) {
 }  // namespace
 
 struct fio_plan_s {
-    int N = 0, q = 0, L = 0, s = 0, lm = 0, dtype = FIO_C64, device = 0;
+    int N = 0, q = 0, L = 0, s = 0, lm = 0, dtype = FIO_C64, device = 0, nrhs_max = 1;
     fio_phase_t phase{};
     int max_box = 0;
-    size_t wbytes = 0;       // bytes of one weight buffer
+    size_t wbytes = 0;       // bytes of one right-hand side's weights (one plane)
+    size_t plane = 0;        // complex values per plane = N^2 q^2
     size_t total_bytes = 0;  // all device memory of the plan
     void *w0 = nullptr, *w1 = nullptr;
     void *dtab = nullptr;    // tables
@@ -184,13 +185,16 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     if (q < QMIN || q > QMAX) return fail(FIO_EINVAL, "q must be in [%d, %d] (got %d)", QMIN, QMAX, q);
     int rc = validate_phase(phase);
     if (rc) return rc;
-    int s = std::min(3, L / 2), lm = L / 2, dtype = FIO_C64;
+    int s = std::min(3, L / 2), lm = L / 2, dtype = FIO_C64, nrhs_max = 1;
     if (opts) {
         if (opts->s != -1) s = opts->s;
         if (opts->lm != -1) lm = opts->lm;
         if (opts->dtype != -1) dtype = opts->dtype;
-        if (opts->nrhs_max != -1 && opts->nrhs_max < 1)
-            return fail(FIO_EINVAL, "nrhs_max must be >= 1 (got %d)", opts->nrhs_max);
+        if (opts->nrhs_max != -1) {
+            if (opts->nrhs_max < 1 || opts->nrhs_max > 4096)
+                return fail(FIO_EINVAL, "nrhs_max must be in [1, 4096] (got %d)", opts->nrhs_max);
+            nrhs_max = opts->nrhs_max;
+        }
     }
     if (s < 0 || s > 3) return fail(FIO_EINVAL, "s must be in [0, 3] (got %d)", s);
     if (!(s <= lm && lm <= L - s)) return fail(FIO_EINVAL, "need s <= lm <= L - s (s=%d, lm=%d, L=%d)", s, lm, L);
@@ -203,6 +207,7 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     p->s = s;
     p->lm = lm;
     p->dtype = dtype;
+    p->nrhs_max = nrhs_max;
     p->phase = *phase;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
@@ -283,9 +288,11 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
 
     // ---- device memory
     const size_t csize = dtype == FIO_C128 ? 16 : 8;
-    p->wbytes = n2 * (size_t)q * q * csize;
+    p->plane = n2 * (size_t)q * q;
+    p->wbytes = p->plane * csize;
     size_t tot = 0;
-    if ((rc = dmalloc(&p->w0, p->wbytes, &tot, "weights 0")) || (rc = dmalloc(&p->w1, p->wbytes, &tot, "weights 1")) ||
+    const size_t wall = p->wbytes * (size_t)nrhs_max;
+    if ((rc = dmalloc(&p->w0, wall, &tot, "weights 0")) || (rc = dmalloc(&p->w1, wall, &tot, "weights 1")) ||
         (rc = dmalloc(&p->dtab, tbytes, &tot, "tables")) ||
         (rc = dmalloc((void **)&p->d_idx, n2 * 4, &tot, "source index")) ||
         (rc = dmalloc((void **)&p->d_p, n2 * sizeof(double2), &tot, "source p")) ||
@@ -339,22 +346,26 @@ int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info) {
     info->n_pairs = (int64_t)plan->N * plan->N;
     info->weights_per_level = (int64_t)plan->N * plan->N * plan->q * plan->q;
     info->workspace_bytes = (int64_t)plan->total_bytes;
+    info->nrhs_max = plan->nrhs_max;
     info->max_box_sources = plan->max_box;
     return FIO_OK;
 }
 
-// Forward pipeline for one right-hand side; stops after `last_stage`
-// (-1: run to the potentials).  Returns the buffer holding the last
-// stage's weights through *wlast.
-static int run_forward(fio_plan_t p, const void *f, void *u, int last_stage, void **wlast, hipStream_t st) {
+// Forward pipeline for `nr` <= nrhs_max right-hand sides (f, u: nr planes of
+// N^2); stops after `last_stage` (-1: run to the potentials) and returns the
+// buffer holding that stage's weights through *wlast.
+static int run_forward(fio_plan_t p, const void *f, void *u, int nr, int last_stage, void **wlast,
+                       hipStream_t st) {
     const PhaseDev ph = to_dev(&p->phase);
     Sources src{p->d_idx, p->d_p, p->d_off};
-    void *a = p->w0, *b = p->w1;
+    const size_t csize = p->dtype == FIO_C128 ? 16 : 8;
+    const size_t fstep = (size_t)p->N * p->N * csize;
+    char *a = (char *)p->w0, *b = (char *)p->w1;
     int stage = 0;
-    hipError_t e;
-    {
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < nr && e == hipSuccess; ++r) {
         Timed tm(p, FIO_K_INIT, st);
-        e = launch_init(p->dtype, p->geom, ph, p->tb, src, f, a, st);
+        e = launch_init(p->dtype, p->geom, ph, p->tb, src, (const char *)f + r * fstep, a + r * p->wbytes, st);
     }
     if (e != hipSuccess) return hip_fail(e, "init launch");
     if (last_stage == stage) {
@@ -364,9 +375,9 @@ static int run_forward(fio_plan_t p, const void *f, void *u, int last_stage, voi
     for (int l = p->s + 1; l <= p->lm; ++l) {
         ++stage;
         {
-        Timed tm(p, FIO_K_PLEVEL, st);
-        e = launch_plevel(p->dtype, p->geom, ph, p->tb, l, a, b, st);
-    }
+            Timed tm(p, FIO_K_PLEVEL, st);
+            e = launch_plevel(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "p-level launch");
         std::swap(a, b);
         if (last_stage == stage) {
@@ -377,7 +388,7 @@ static int run_forward(fio_plan_t p, const void *f, void *u, int last_stage, voi
     ++stage;
     {
         Timed tm(p, FIO_K_SWITCH, st);
-        e = launch_switch(p->dtype, p->geom, ph, p->tb, a, st);
+        e = launch_switch(p->dtype, p->geom, ph, p->tb, a, nr, p->plane, st);
     }
     if (e != hipSuccess) return hip_fail(e, "switch launch");
     if (last_stage == stage) {
@@ -387,9 +398,9 @@ static int run_forward(fio_plan_t p, const void *f, void *u, int last_stage, voi
     for (int l = p->lm + 1; l <= p->L - p->s; ++l) {
         ++stage;
         {
-        Timed tm(p, FIO_K_XLEVEL, st);
-        e = launch_xlevel(p->dtype, p->geom, ph, p->tb, l, a, b, st);
-    }
+            Timed tm(p, FIO_K_XLEVEL, st);
+            e = launch_xlevel(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "x-level launch");
         std::swap(a, b);
         if (last_stage == stage) {
@@ -398,48 +409,50 @@ static int run_forward(fio_plan_t p, const void *f, void *u, int last_stage, voi
         }
     }
     if (last_stage >= 0) return fail(FIO_EINVAL, "stage %d out of range (last is %d)", last_stage, stage);
-    {
+    for (int r = 0; r < nr && e == hipSuccess; ++r) {
         Timed tm(p, FIO_K_TERM, st);
-        e = launch_term(p->dtype, p->geom, ph, p->tb, a, u, st);
+        e = launch_term(p->dtype, p->geom, ph, p->tb, a + r * p->wbytes, (char *)u + r * fstep, st);
     }
     if (e != hipSuccess) return hip_fail(e, "termination launch");
     return FIO_OK;
 }
 
-static int run_adjoint(fio_plan_t p, const void *u, void *f, hipStream_t st) {
+static int run_adjoint(fio_plan_t p, const void *u, void *f, int nr, hipStream_t st) {
     const PhaseDev ph = to_dev(&p->phase);
     Sources src{p->d_idx, p->d_p, p->d_off};
-    void *a = p->w0, *b = p->w1;
-    hipError_t e;
-    {
+    const size_t csize = p->dtype == FIO_C128 ? 16 : 8;
+    const size_t fstep = (size_t)p->N * p->N * csize;
+    char *a = (char *)p->w0, *b = (char *)p->w1;
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < nr && e == hipSuccess; ++r) {
         Timed tm(p, FIO_K_TERM_ADJ, st);
-        e = launch_term_adj(p->dtype, p->geom, ph, p->tb, u, a, st);
+        e = launch_term_adj(p->dtype, p->geom, ph, p->tb, (const char *)u + r * fstep, a + r * p->wbytes, st);
     }
     if (e != hipSuccess) return hip_fail(e, "termination^H launch");
     for (int l = p->L - p->s; l >= p->lm + 1; --l) {
         {
-        Timed tm(p, FIO_K_XLEVEL_ADJ, st);
-        e = launch_xlevel_adj(p->dtype, p->geom, ph, p->tb, l, a, b, st);
-    }
+            Timed tm(p, FIO_K_XLEVEL_ADJ, st);
+            e = launch_xlevel_adj(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "x-level^H launch");
         std::swap(a, b);
     }
     {
         Timed tm(p, FIO_K_SWITCH_ADJ, st);
-        e = launch_switch_adj(p->dtype, p->geom, ph, p->tb, a, st);
+        e = launch_switch_adj(p->dtype, p->geom, ph, p->tb, a, nr, p->plane, st);
     }
     if (e != hipSuccess) return hip_fail(e, "switch^H launch");
     for (int l = p->lm; l >= p->s + 1; --l) {
         {
-        Timed tm(p, FIO_K_PLEVEL_ADJ, st);
-        e = launch_plevel_adj(p->dtype, p->geom, ph, p->tb, l, a, b, st);
-    }
+            Timed tm(p, FIO_K_PLEVEL_ADJ, st);
+            e = launch_plevel_adj(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "p-level^H launch");
         std::swap(a, b);
     }
-    {
+    for (int r = 0; r < nr && e == hipSuccess; ++r) {
         Timed tm(p, FIO_K_INIT_ADJ, st);
-        e = launch_init_adj(p->dtype, p->geom, ph, p->tb, src, a, f, st);
+        e = launch_init_adj(p->dtype, p->geom, ph, p->tb, src, a + r * p->wbytes, (char *)f + r * fstep, st);
     }
     if (e != hipSuccess) return hip_fail(e, "initialisation^H launch");
     return FIO_OK;
@@ -455,8 +468,9 @@ int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream) {
     if ((rc = set_device(plan))) return rc;
     const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
     hipStream_t st = (hipStream_t)stream;
-    for (int r = 0; r < nrhs; ++r) {
-        rc = run_forward(plan, (const char *)f + r * step, (char *)u + r * step, -1, nullptr, st);
+    for (int r = 0; r < nrhs; r += plan->nrhs_max) {
+        const int nr = std::min(plan->nrhs_max, nrhs - r);
+        rc = run_forward(plan, (const char *)f + r * step, (char *)u + r * step, nr, -1, nullptr, st);
         if (rc) return rc;
     }
     return FIO_OK;
@@ -472,8 +486,9 @@ int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, void *s
     if ((rc = set_device(plan))) return rc;
     const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
     hipStream_t st = (hipStream_t)stream;
-    for (int r = 0; r < nrhs; ++r) {
-        rc = run_adjoint(plan, (const char *)u + r * step, (char *)f + r * step, st);
+    for (int r = 0; r < nrhs; r += plan->nrhs_max) {
+        const int nr = std::min(plan->nrhs_max, nrhs - r);
+        rc = run_adjoint(plan, (const char *)u + r * step, (char *)f + r * step, nr, st);
         if (rc) return rc;
     }
     return FIO_OK;
@@ -489,7 +504,7 @@ int fio_debug_stage(fio_plan_t plan, const void *f, int stage, void *weights, vo
     if ((rc = set_device(plan))) return rc;
     hipStream_t st = (hipStream_t)stream;
     void *wl = nullptr;
-    if ((rc = run_forward(plan, f, nullptr, stage, &wl, st))) return rc;
+    if ((rc = run_forward(plan, f, nullptr, 1, stage, &wl, st))) return rc;
     hipError_t e = hipMemcpyAsync(weights, wl, plan->wbytes, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "weights copy");
     return FIO_OK;
