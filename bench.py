@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--q", type=int, default=9)
     ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--contract", choices=["fp", "bf16"], default="fp",
+                    help="interpolation contractions: FP32 vector ALUs or BF16 MFMA (FP32 accumulation)")
     ap.add_argument("--rows", type=int, default=256, help="sampled points for eq:err and the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -74,7 +76,7 @@ def main():
 
     torch.cuda.set_device(0)
     N, q, R = args.N, args.q, args.nrhs
-    plan = fio.Plan(N, q, fio.Phase(), dtype=torch.complex64, nrhs_max=R)
+    plan = fio.Plan(N, q, fio.Phase(), dtype=torch.complex64, nrhs_max=R, contract=args.contract)
     f_host = white_noise(N, 3, nrhs=R)
     f = torch.as_tensor(f_host).to(torch.complex64).cuda()
     u = torch.empty_like(f)
@@ -155,7 +157,7 @@ def main():
         "config": {"workload": f"eq:ex1 FIO butterfly N={N} q={q} s={plan.s} lm={plan.lm}, "
                                f"complex white-noise f, forward+adjoint per step",
                    "N": N, "q": q, "nrhs": R, "s": plan.s, "lm": plan.lm, "phase_dtype": "f64",
-                   "weight_dtype": "f32"},
+                   "weight_dtype": "f32", "contract": args.contract},
         "plain_forward_applies_per_s": plain,
         "rel_err_vs_direct_sum": rel_err,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},

@@ -77,6 +77,15 @@ typedef struct {
 #define FIO_C128 0
 #define FIO_C64  1
 
+/* Contraction precision of the interpolation passes (FIO_C64 plans only):
+ * FIO_CONTRACT_FP:   FP32 on the vector ALUs (default);
+ * FIO_CONTRACT_BF16: operands rounded to BF16, products accumulated in FP32
+ *                    on the matrix cores (MFMA), right-hand sides in tiles
+ *                    of 16; kernel values and all other steps stay FP32/FP64.
+ *                    Requires q <= 12.                                     */
+#define FIO_CONTRACT_FP   0
+#define FIO_CONTRACT_BF16 1
+
 typedef struct fio_plan_s *fio_plan_t;
 
 /* Options for fio_plan_ex.  Any field set to -1 takes its default. */
@@ -93,11 +102,12 @@ typedef struct {
                      take nrhs in chunks of nrhs_max, computing every kernel
                      value of the levels and the switch once per chunk (the
                      vectorised butterfly of Sec. 4, last paragraphs)        */
+    int contract; /* FIO_CONTRACT_FP (default) or FIO_CONTRACT_BF16           */
 } fio_plan_opts_t;
 
 /* Geometry and sizes of a plan. */
 typedef struct {
-    int N, q, L, s, lm, dtype;
+    int N, q, L, s, lm, dtype, contract;
     int64_t n_pairs;          /* box pairs per level = N^2                        */
     int64_t weights_per_level;/* complex weights per level per RHS = N^2 q^2      */
     int64_t workspace_bytes;  /* device memory owned by the plan                  */

@@ -32,6 +32,8 @@ FOURIER = 0
 ELLIPSE = 1
 C128 = 0
 C64 = 1
+CONTRACT_FP = 0
+CONTRACT_BF16 = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfio.so")
@@ -70,12 +72,13 @@ class _CPhase(ctypes.Structure):
 
 class _COpts(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int), ("lm", ctypes.c_int), ("dtype", ctypes.c_int),
-                ("nrhs_max", ctypes.c_int)]
+                ("nrhs_max", ctypes.c_int), ("contract", ctypes.c_int)]
 
 
 class _CInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("q", ctypes.c_int), ("L", ctypes.c_int), ("s", ctypes.c_int),
-                ("lm", ctypes.c_int), ("dtype", ctypes.c_int), ("n_pairs", ctypes.c_int64),
+                ("lm", ctypes.c_int), ("dtype", ctypes.c_int), ("contract", ctypes.c_int),
+                ("n_pairs", ctypes.c_int64),
                 ("weights_per_level", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("max_box_sources", ctypes.c_int), ("nrhs_max", ctypes.c_int)]
 
@@ -129,18 +132,25 @@ class Plan:
     (defaults min(3, L/2) and L/2); dtype: torch.complex64 (FP32 weights,
     FP64 phases) or torch.complex128 (FP64 throughout); nrhs_max: right-hand
     sides processed together, sharing every kernel value of the levels and
-    the switch (the plan holds 2 x nrhs_max x N^2 q^2 complex weights).
+    the switch (the plan holds 2 x nrhs_max x N^2 q^2 complex weights);
+    contract: "fp" (contractions in the weight precision on the vector ALUs)
+    or "bf16" (BF16 operands, FP32 accumulation on the matrix cores;
+    complex64 plans, q <= 12).
     """
 
     def __init__(self, N: int, q: int, phase: Phase = Phase(), s: int | None = None,
-                 lm: int | None = None, dtype: torch.dtype = torch.complex64, nrhs_max: int = 1):
+                 lm: int | None = None, dtype: torch.dtype = torch.complex64, nrhs_max: int = 1,
+                 contract: str = "fp"):
         lib = load_library()
         if dtype not in (torch.complex64, torch.complex128):
             raise ValueError("dtype must be torch.complex64 or torch.complex128")
         self.dtype = dtype
         self.device = torch.device("cuda", torch.cuda.current_device())
+        if contract not in ("fp", "bf16"):
+            raise ValueError('contract must be "fp" or "bf16"')
         opts = _COpts(-1 if s is None else int(s), -1 if lm is None else int(lm),
-                      C64 if dtype == torch.complex64 else C128, int(nrhs_max))
+                      C64 if dtype == torch.complex64 else C128, int(nrhs_max),
+                      CONTRACT_BF16 if contract == "bf16" else CONTRACT_FP)
         h = ctypes.c_void_p()
         _check(lib.fio_plan_ex(int(N), int(q), ctypes.byref(_cphase(phase)), ctypes.byref(opts),
                                ctypes.byref(h)), "fio_plan_ex")
@@ -152,6 +162,7 @@ class Plan:
         self.workspace_bytes = int(info.workspace_bytes)
         self.max_box_sources = int(info.max_box_sources)
         self.nrhs_max = int(info.nrhs_max)
+        self.contract = contract
         self.n_stages = self.L - 2 * self.s + 2
 
     # -- lifetime ---------------------------------------------------------

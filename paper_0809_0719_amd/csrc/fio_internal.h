@@ -65,6 +65,12 @@ hipError_t launch_xlevel(int dtype, const Geom &g, const PhaseDev &ph, const Tab
 hipError_t launch_term(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
                        const void *w_in, void *u, hipStream_t st);
 
+// Batched level kernels with BF16 MFMA contractions (fio_kernels_mfma.hip),
+// complex64 weights; mfma_supported_q tells which q they are built for.
+bool mfma_supported_q(int q);
+hipError_t launch_plevel_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
+                              const void *w_in, void *w_out, int nrhs, size_t plane, hipStream_t st);
+
 // Adjoint launchers: exact conjugate transposes of the above.
 hipError_t launch_term_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
                            const void *u, void *w_out, hipStream_t st);

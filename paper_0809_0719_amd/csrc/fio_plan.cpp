@@ -83,6 +83,7 @@ double lagrange(const std::vector<double> &z, int t, double u) {
 
 struct fio_plan_s {
     int N = 0, q = 0, L = 0, s = 0, lm = 0, dtype = FIO_C64, device = 0, nrhs_max = 1;
+    int contract = FIO_CONTRACT_FP;
     fio_phase_t phase{};
     int max_box = 0;
     size_t wbytes = 0;       // bytes of one right-hand side's weights (one plane)
@@ -185,8 +186,9 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     if (q < QMIN || q > QMAX) return fail(FIO_EINVAL, "q must be in [%d, %d] (got %d)", QMIN, QMAX, q);
     int rc = validate_phase(phase);
     if (rc) return rc;
-    int s = std::min(3, L / 2), lm = L / 2, dtype = FIO_C64, nrhs_max = 1;
+    int s = std::min(3, L / 2), lm = L / 2, dtype = FIO_C64, nrhs_max = 1, contract = FIO_CONTRACT_FP;
     if (opts) {
+        if (opts->contract != -1) contract = opts->contract;
         if (opts->s != -1) s = opts->s;
         if (opts->lm != -1) lm = opts->lm;
         if (opts->dtype != -1) dtype = opts->dtype;
@@ -199,6 +201,10 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     if (s < 0 || s > 3) return fail(FIO_EINVAL, "s must be in [0, 3] (got %d)", s);
     if (!(s <= lm && lm <= L - s)) return fail(FIO_EINVAL, "need s <= lm <= L - s (s=%d, lm=%d, L=%d)", s, lm, L);
     if (dtype != FIO_C64 && dtype != FIO_C128) return fail(FIO_EINVAL, "unknown dtype %d", dtype);
+    if (contract != FIO_CONTRACT_FP && contract != FIO_CONTRACT_BF16)
+        return fail(FIO_EINVAL, "unknown contraction precision %d", contract);
+    if (contract == FIO_CONTRACT_BF16 && (dtype != FIO_C64 || !mfma_supported_q(q)))
+        return fail(FIO_EINVAL, "BF16 contractions need dtype FIO_C64 and q <= 12 (dtype %d, q %d)", dtype, q);
 
     fio_plan_s *p = new fio_plan_s();
     p->N = N;
@@ -208,6 +214,7 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     p->lm = lm;
     p->dtype = dtype;
     p->nrhs_max = nrhs_max;
+    p->contract = contract;
     p->phase = *phase;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
@@ -343,6 +350,7 @@ int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info) {
     info->s = plan->s;
     info->lm = plan->lm;
     info->dtype = plan->dtype;
+    info->contract = plan->contract;
     info->n_pairs = (int64_t)plan->N * plan->N;
     info->weights_per_level = (int64_t)plan->N * plan->N * plan->q * plan->q;
     info->workspace_bytes = (int64_t)plan->total_bytes;
@@ -376,7 +384,9 @@ static int run_forward(fio_plan_t p, const void *f, void *u, int nr, int last_st
         ++stage;
         {
             Timed tm(p, FIO_K_PLEVEL, st);
-            e = launch_plevel(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
+            e = p->contract == FIO_CONTRACT_BF16
+                    ? launch_plevel_mfma(p->geom, ph, p->tb, l, a, b, nr, p->plane, st)
+                    : launch_plevel(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
         }
         if (e != hipSuccess) return hip_fail(e, "p-level launch");
         std::swap(a, b);
