@@ -40,14 +40,75 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
-def switch_lane_ops_per_pair(q: int) -> int:
-    """Minimum VALU lane-ops of one switch pair (eq:alg2m) as the kernel
-    formulates it: per (t, s2) one direction phase G = Phi(x_t, e(theta_s2))
-    (2 FMA, 2 mul, 1 add, 1 square root = 9), 1 + q//2 exponentials (FP64
-    product, round, subtract, convert = 4; sine + cosine = 8), q//2 paired
-    complex-by-(real,imag) updates (4 FMA) and one complex multiply-add (4)."""
+# Algorithmic VALU lane-operations per launch of every kernel kind.  Unit
+# costs: an exponential of an FP64-reduced phase = 12 (FP64 product, round,
+# subtract, convert = 4; sine + cosine at quarter rate = 8); a direction or
+# Cartesian phase = 9 (2 FMA, 2 mul, 1 add, square root = 4); a real-by-
+# complex multiply-add = 2; a complex product or multiply-add = 4.  Kernel
+# values shared by a chunk of right-hand sides are counted once per chunk.
+EXP, PHS, CRMAC, CMUL = 12, 9, 2, 4
+
+
+def lane_ops(kind: str, N: int, q: int, s: int, nrhs: int, rc_switch: int = 8, rc_switch_adj: int = 2) -> float:
+    n2 = float(N) * N
     h = q // 2
-    return q ** 3 * (9 + 12 * (1 + h) + 4 * h + 4)
+    m = 1 << s
+    nA = 4 ** s
+    if kind in ("plevel", "plevel_adj", "xlevel", "xlevel_adj"):
+        shared = 5 * q * q * EXP + 3 * q * PHS if kind.startswith("p") else 5 * q * q * EXP + 2.5 * q * q * PHS
+        per_rhs = 6 * q ** 3 * CRMAC + 5 * q * q * CMUL
+        return n2 * (shared + nrhs * per_rhs)
+    if kind in ("switch", "switch_adj"):
+        rc = 1 if nrhs == 1 else (rc_switch if kind == "switch" else rc_switch_adj)
+        chunks = -(-nrhs // rc)
+        shared = q ** 3 * (PHS + (1 + h) * EXP)
+        per_rhs = q ** 3 * (4 * h + 4)
+        return n2 * (chunks * shared + nrhs * per_rhs)
+    if kind in ("init", "init_adj"):
+        # per (A, source): phase + exponential + product + q^2 + q multiply-adds;
+        # per (A, B box): q^2 remodulation exponentials and products
+        per_rhs = nA * n2 * (PHS + EXP + CMUL + (q * q + q) * CRMAC) + nA * (n2 / nA) * q * q * (EXP + CMUL)
+        return nrhs * per_rhs
+    if kind in ("term", "term_adj"):
+        # per (A, B): q^2 prefactors, the two 1-D passes, m^2 factors E(x, p0(B))
+        pairs = n2
+        per_pair = q * q * (PHS + EXP + CMUL) + (q * q * m + m * m * q) * CRMAC + m * m * (PHS + EXP + CMUL)
+        return nrhs * pairs * per_pair
+    raise ValueError(kind)
+
+
+def traffic_from_profiles(kernel: str, config: dict):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources and the same
+    configuration (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if any(t.get("config", {}).get(k) != v for k, v in config.items()):
+        return None
+    h = hashlib.sha256()
+    for f in sorted(t.get("sources", [])):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t.get("sources_sha256"):
+        return None
+    return t.get("bytes_per_launch", {}).get(kernel)
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
+    """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    torch.cuda.set_device(0)
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
 
 
 def main():
@@ -57,12 +118,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--q", type=int, default=9)
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--contract", choices=["fp", "bf16"], default="fp",
                     help="interpolation contractions: FP32 vector ALUs or BF16 MFMA (FP32 accumulation)")
     ap.add_argument("--rows", type=int, default=256, help="sampled points for eq:err and the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (for scaling the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calib:
+        copy_calibration()
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the butterfly pass here is a single-GPU build "
@@ -117,19 +183,26 @@ def main():
     torch.cuda.synchronize()
     plain = nplain / (time.perf_counter() - t2)
 
-    # roofline of the dominant kernel (largest share of the timed region)
+    # roofline of every kernel kind, and of the dominant one (largest share of
+    # the timed region): algorithmic VALU lane-ops per launch / average launch time
+    per_kind = {}
+    for kind, (k_ms, k_n) in prof.items():
+        avg_ms = k_ms / k_n
+        # one launch covers nrhs right-hand sides for the level and switch
+        # kernels, one right-hand side for initialisation and termination
+        per_launch_rhs = R if kind in ("plevel", "plevel_adj", "xlevel", "xlevel_adj", "switch",
+                                       "switch_adj") else 1
+        ops = lane_ops(kind, N, q, plan.s, per_launch_rhs)
+        ach = ops / (avg_ms * 1e-3) / 1e12
+        per_kind[kind] = {"avg_ms": avg_ms, "launches": k_n, "achieved_Tlane_op_s": ach,
+                          "frac": ach / VALU_PEAK_TOPS}
     kind = max(prof, key=lambda k: prof[k][0])
-    k_ms, k_n = prof[kind]
-    avg_ms = k_ms / k_n
-    if kind in ("switch", "switch_adj"):
-        ops = switch_lane_ops_per_pair(q) * N * N
-        achieved = ops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": f"k_{kind}", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                "avg_ms": avg_ms, "launches": k_n}
-    else:
-        roof = {"bound": "alu", "kernel": f"k_{kind}", "achieved": None, "peak": VALU_PEAK_TOPS,
-                "unit": "Tlane-op/s", "frac": None, "traffic": None, "avg_ms": avg_ms, "launches": k_n}
+    kk = per_kind[kind]
+    roof = {"bound": "alu", "kernel": f"k_{kind}", "achieved": kk["achieved_Tlane_op_s"],
+            "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": kk["frac"],
+            "traffic": traffic_from_profiles(f"k_{kind}", {"N": N, "q": q, "nrhs": R, "dtype": "complex64",
+                                                          "contract": args.contract}),
+            "avg_ms": kk["avg_ms"], "launches": kk["launches"]}
 
     # accuracy: eq:err on sampled points against the FP64 direct sum, and the CPU baseline
     rows = sample_points(N, args.rows, seed=103)
@@ -161,6 +234,7 @@ def main():
         "plain_forward_applies_per_s": plain,
         "rel_err_vs_direct_sum": rel_err,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "kernel_roofline": per_kind,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
