@@ -154,6 +154,27 @@ int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream);
  * u(x).  Same layouts and rules as fio_apply with the roles of f, u swapped. */
 int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, void *stream);
 
+/* Forward butterfly with its derivatives with respect to the velocity
+ * scalings a1, a2 of the ellipse phase (Sec. 5, eq:ex1 family), at the
+ * plan's current phase: for every right-hand side r
+ *     u[r]      = B f[r]                (as fio_apply, to rounding),
+ *     du_da1[r] = d(B f[r]) / d a1,     du_da2[r] = d(B f[r]) / d a2,
+ * the exact derivatives of the butterfly approximation itself (every kernel
+ * value E = exp(2 pi i Phi) of Sec. 4 differentiated, the Chebyshev grids
+ * and tables held fixed), by forward-mode propagation of two tangent weight
+ * sets beside the primal one.  For FIO_PHASE_FOURIER both derivatives are 0.
+ *   f: device, nrhs x N x N complex (plan dtype), read only.
+ *   u: device, nrhs x N x N, or NULL (then the primal output is not stored).
+ *   du_da1, du_da2: device, nrhs x N x N each; fully overwritten.
+ *   The outputs must not overlap f or each other.  Requires q <= 12.
+ * Workspace: three N^2 q^2 planes in each of two buffers -- the plan's own
+ * weight buffers when nrhs_max >= 3, else two buffers the first call
+ * allocates and the plan keeps until fio_destroy (FIO_ENOMEM if that fails).
+ * The right-hand sides are processed one after another.  Asynchronous on
+ * `stream`; FIO_EINVAL before any launch on bad arguments. */
+int fio_apply_dphase(fio_plan_t plan, const void *f, void *u, void *du_da1, void *du_da2, int nrhs,
+                     void *stream);
+
 /* Diagnostics: run the forward pipeline for one right-hand side up to and
  * including stage `stage` and copy that stage's weights to `weights`.
  *   stage 0                 : initialisation, level s
@@ -185,7 +206,8 @@ int fio_debug_stage(fio_plan_t plan, const void *f, int stage, void *weights, vo
 #define FIO_K_SWITCH_ADJ  7
 #define FIO_K_PLEVEL_ADJ  8
 #define FIO_K_INIT_ADJ    9
-#define FIO_KERNEL_KINDS 10
+#define FIO_K_TANGENT    10  /* every kernel of fio_apply_dphase */
+#define FIO_KERNEL_KINDS 11
 
 int fio_profile_enable(fio_plan_t plan, int enable);
 int fio_profile_read(fio_plan_t plan, double *ms, int64_t *launches, int n);

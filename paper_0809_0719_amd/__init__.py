@@ -14,6 +14,7 @@ If the library is missing the calls raise; there is no CPU fallback.
     >>> u = plan.apply(f)                          # f: (N, N) or (R, N, N) complex64 on cuda
     >>> g = plan.adjoint(u)                        # B^H u
     >>> u = fio_apply(f, plan)                     # autograd: backward is the adjoint
+    >>> u = fio_apply(f, plan, a)                  # a = (a1, a2): gradients for the phase too
 """
 from __future__ import annotations
 
@@ -24,7 +25,7 @@ from dataclasses import dataclass
 import torch
 
 __all__ = [
-    "Phase", "Plan", "FIOApply", "fio_apply", "load_library", "library_path",
+    "Phase", "Plan", "FIOApply", "FIOApplyPhase", "fio_apply", "load_library", "library_path",
     "FOURIER", "ELLIPSE", "C128", "C64", "EXPORTED_SYMBOLS",
 ]
 
@@ -42,12 +43,13 @@ _LIB_PATH = os.path.join(_HERE, "libfio.so")
 EXPORTED_SYMBOLS = (
     "fio_plan", "fio_plan_ex", "fio_set_phase", "fio_plan_get_info", "fio_apply",
     "fio_apply_adjoint", "fio_debug_stage", "fio_destroy", "fio_last_error",
-    "fio_profile_enable", "fio_profile_read",
+    "fio_profile_enable", "fio_profile_read", "fio_apply_dphase",
 )
 
 # kernel kinds of fio_profile_read (FIO_K_* in include/fio.h)
 KERNEL_KINDS = ("init", "plevel", "switch", "xlevel", "term",
-                "term_adj", "xlevel_adj", "switch_adj", "plevel_adj", "init_adj")
+                "term_adj", "xlevel_adj", "switch_adj", "plevel_adj", "init_adj",
+                "tangent")
 
 
 def library_path() -> str:
@@ -102,6 +104,7 @@ def load_library():
     lib.fio_plan_get_info.argtypes = [vp, ctypes.POINTER(_CInfo)]
     lib.fio_apply.argtypes = [vp, vp, vp, i, vp]
     lib.fio_apply_adjoint.argtypes = [vp, vp, vp, i, vp]
+    lib.fio_apply_dphase.argtypes = [vp, vp, vp, vp, vp, i, vp]
     lib.fio_debug_stage.argtypes = [vp, vp, i, vp, vp]
     lib.fio_destroy.argtypes = [vp]
     lib.fio_profile_enable.argtypes = [vp, i]
@@ -218,6 +221,21 @@ class Plan:
                "fio_apply_adjoint")
         return f
 
+    def apply_dphase(self, f: torch.Tensor, primal: bool = True):
+        """(u, du/da1, du/da2) for f of shape (..., N, N): the butterfly and its
+        exact derivatives with respect to the velocity scalings of the phase
+        (u is None when ``primal`` is False).  Requires q <= 12."""
+        f, nrhs = self._prep(f, "f")
+        u = torch.empty_like(f) if primal else None
+        d1 = torch.empty_like(f)
+        d2 = torch.empty_like(f)
+        if nrhs == 0:
+            return u, d1, d2
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().fio_apply_dphase(self._h, f.data_ptr(), None if u is None else u.data_ptr(),
+                                               d1.data_ptr(), d2.data_ptr(), nrhs, st), "fio_apply_dphase")
+        return u, d1, d2
+
     def debug_stage(self, f: torch.Tensor, stage: int) -> torch.Tensor:
         """Weights after forward stage ``stage`` (layout in include/fio.h)."""
         f, nrhs = self._prep(f, "f")
@@ -263,5 +281,41 @@ class FIOApply(torch.autograd.Function):
         return ctx.plan.adjoint(grad_u.contiguous()), None
 
 
-def fio_apply(f: torch.Tensor, plan: Plan) -> torch.Tensor:
-    return FIOApply.apply(f, plan)
+class FIOApplyPhase(torch.autograd.Function):
+    """u = B(a) f with the velocity scalings a = (a1, a2) of the ellipse phase
+    as a second differentiable input.  Backward: grad_f = B^H grad_u, and
+    grad_a_j = Re <grad_u, du/da_j> with du/da_j from the forward-mode
+    tangent pass (two parameters, so one tangent pass per right-hand side)."""
+
+    @staticmethod
+    def forward(ctx, f: torch.Tensor, a: torch.Tensor, plan: Plan):
+        a1, a2 = (float(v) for v in a.detach().to("cpu", torch.float64))
+        ph = plan.phase
+        phase = Phase(ph.kind, a1, a2, ph.eta1, ph.eta2)
+        plan.set_phase(phase)
+        ctx.plan, ctx.phase, ctx.a_meta = plan, phase, (a.device, a.dtype)
+        ctx.save_for_backward(f)
+        return plan.apply(f)
+
+    @staticmethod
+    def backward(ctx, grad_u: torch.Tensor):
+        plan = ctx.plan
+        (f,) = ctx.saved_tensors
+        plan.set_phase(ctx.phase)
+        grad_u = grad_u.contiguous()
+        grad_f = grad_a = None
+        if ctx.needs_input_grad[0]:
+            grad_f = plan.adjoint(grad_u)
+        if ctx.needs_input_grad[1]:
+            _, d1, d2 = plan.apply_dphase(f, primal=False)
+            g = torch.stack([torch.sum((grad_u.conj() * d).real.double()) for d in (d1, d2)])
+            grad_a = g.to(device=ctx.a_meta[0], dtype=ctx.a_meta[1])
+        return grad_f, grad_a, None
+
+
+def fio_apply(f: torch.Tensor, plan: Plan, a: torch.Tensor | None = None) -> torch.Tensor:
+    """u = B f with autograd.  With ``a`` (a real tensor (a1, a2)), the plan's
+    ellipse velocity scalings are set to ``a`` and ``a`` gets gradients too."""
+    if a is None:
+        return FIOApply.apply(f, plan)
+    return FIOApplyPhase.apply(f, a, plan)

@@ -1,5 +1,6 @@
 // Internal definitions shared by the host plan (fio_plan.cpp) and the HIP
-// kernels (fio_kernels_fwd.hip, fio_kernels_adj.hip).  Not part of the public ABI.
+// kernels (fio_kernels_fwd.hip, fio_kernels_adj.hip, fio_kernels_mfma.hip,
+// fio_kernels_tan.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -82,5 +83,15 @@ hipError_t launch_plevel_adj(int dtype, const Geom &g, const PhaseDev &ph, const
                              const void *w_in, void *w_out, int nrhs, size_t plane, hipStream_t st);
 hipError_t launch_init_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
                            const Sources &src, const void *w_in, void *f, hipStream_t st);
+
+// Forward pass with the derivatives with respect to the phase's velocity
+// scalings (fio_kernels_tan.hip), one right-hand side: weights are three
+// planes `plane` complex values apart (primal, d/da1, d/da2).  `step`:
+// 0 initialisation (in = f), 1 p-level, 2 switch (in place on out),
+// 3 x-level, 4 termination (out = u or NULL, u1 = du/da1, u2 = du/da2).
+bool tangent_supported_q(int q);
+hipError_t launch_tangent_step(int dtype, int step, const Geom &g, const PhaseDev &ph, const Tables &tb,
+                               const Sources &src, int level, const void *in, void *out, size_t plane,
+                               void *u1, void *u2, hipStream_t st);
 
 }  // namespace fio

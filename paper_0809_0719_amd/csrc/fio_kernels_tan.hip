@@ -1,0 +1,698 @@
+// Forward-mode derivatives of the butterfly with respect to the phase's
+// velocity scalings (a1, a2): every kernel here carries three weight planes
+// through one step of Sec. 4 -- the primal delta and its derivatives
+// d delta / d a1, d delta / d a2 -- sharing the kernel values.  A kernel
+// value E = exp(2 pi i Phi) contributes dE/da = 2 pi i (dPhi/da) E, so a
+// step out = F(in) with factors E gives
+//     d out = F(d in) + (the same step with one E replaced by dE/da) (in),
+// summed over its factors (product rule).  The weights are recomputed for
+// every call, never stored.
+//
+// For the ellipse phase Phi(x, e) = x.e + sqrt(C1 e1^2 + C2 e2^2) with
+// C_j = (a_j c_j(x))^2: dPhi/da1 = C1 e1^2 / (a1 sqrt(.)), dPhi/da2 =
+// C2 e2^2 / (a2 sqrt(.)); the Fourier phase does not depend on a (C = 0).
+#include <hip/hip_runtime.h>
+
+#include "fio_kernels_common.h"
+
+namespace fio {
+
+struct G3 {
+    double g, d1, d2;  // Phi and its derivatives with respect to a1, a2
+};
+
+__device__ __forceinline__ G3 phase_dir3(const XP &x, const PhaseDev &ph, double ct, double st) {
+    const double S = sqrt(fma(x.C1 * ct, ct, x.C2 * st * st));
+    G3 r;
+    r.g = fma(x.x1, ct, x.x2 * st) + S;
+    r.d1 = (S > 0.0 && x.C1 > 0.0) ? x.C1 * ct * ct / (ph.a1 * S) : 0.0;
+    r.d2 = (S > 0.0 && x.C2 > 0.0) ? x.C2 * st * st / (ph.a2 * S) : 0.0;
+    return r;
+}
+
+__device__ __forceinline__ G3 phase_cart3(const XP &x, const PhaseDev &ph, double k1, double k2) {
+    const double S = sqrt(fma(x.C1 * k1, k1, x.C2 * k2 * k2));
+    G3 r;
+    r.g = fma(x.x1, k1, x.x2 * k2) + S;
+    r.d1 = (S > 0.0 && x.C1 > 0.0) ? x.C1 * k1 * k1 / (ph.a1 * S) : 0.0;
+    r.d2 = (S > 0.0 && x.C2 > 0.0) ? x.C2 * k2 * k2 / (ph.a2 * S) : 0.0;
+    return r;
+}
+
+// 2 pi i phi z
+template <typename T>
+__device__ __forceinline__ cpx<T> i2pi(double phi, cpx<T> z) {
+    const T s = (T)(6.283185307179586476925286766559 * phi);
+    return {-s * z.im, s * z.re};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) {
+    return {a.re + b.re, a.im + b.im};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) {
+    return {a.re - b.re, a.im - b.im};
+}
+
+constexpr int SCT = 16;  // sources per chunk in the tangent initialisation
+
+// ===========================================================================
+// initialisation (eq:alg2a) with derivatives:
+//   out   = conj Er . acc0,  acc0 = sum_p L(p) E(x0,p) f(p)
+//   d out = conj Er . acc_k - 2 pi i rho dG_k . out,  acc_k = sum_p L(p) 2 pi i dPhi_k(x0,p) E(x0,p) f(p)
+// ===========================================================================
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k_init_tan(Geom g, PhaseDev ph, Tables tb, Sources src,
+                                                 const cpx<T> *__restrict__ f, cpx<T> *__restrict__ w,
+                                                 size_t plane) {
+    constexpr int ACH = (NT / Q) < 64 ? (NT / Q) : 64;
+    __shared__ T lag1[SCT][Q];
+    __shared__ T lag2[SCT][Q];
+    __shared__ cpx<T> gA[3][ACH][SCT];
+    __shared__ double2 kk[SCT];
+    __shared__ cpx<T> fs[SCT];
+    __shared__ double zs[Q], ls[Q];
+    __shared__ XP xA[ACH];
+
+    const int tid = threadIdx.x;
+    const int lB = g.L - g.s;
+    const uint32_t mB = blockIdx.x;
+    const int nA = 1 << (2 * g.s);
+    const int a0 = blockIdx.y * ACH;
+    const int nAc = min(ACH, nA - a0);
+    const int aL = tid / Q, t1 = tid - aL * Q;
+    const bool active = aL < nAc;
+
+    if (tid < Q) {
+        zs[tid] = tb.z[tid];
+        ls[tid] = tb.lam[tid];
+    }
+    if (tid < nAc) {
+        int a1, a2;
+        morton_decode((uint32_t)(a0 + tid), a1, a2);
+        xA[tid] = make_xp(ph, box_centre(a1, g.s), box_centre(a2, g.s));
+    }
+    int bp1, bp2;
+    morton_decode(mB, bp1, bp2);
+    const double scale = ldexp(1.0, lB);
+
+    cpx<T> acc[3][Q];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int t = 0; t < Q; ++t) acc[k][t] = {(T)0, (T)0};
+
+    const int beg = src.off[mB], end = src.off[mB + 1];
+    __syncthreads();
+    for (int c0 = beg; c0 < end; c0 += SCT) {
+        const int n = min(SCT, end - c0);
+        if (tid < n) {
+            const int j = c0 + tid;
+            const int idx = src.idx[j];
+            const double2 p = src.p[j];
+            lagrange_row<T, Q>(p.x * scale - ((double)bp1 + 0.5), zs, ls, lag1[tid]);
+            lagrange_row<T, Q>(p.y * scale - ((double)bp2 + 0.5), zs, ls, lag2[tid]);
+            kk[tid] = make_double2((double)(idx / g.N - g.N / 2), (double)(idx % g.N - g.N / 2));
+            fs[tid] = f[idx];
+        }
+        __syncthreads();
+        for (int it = tid; it < nAc * n; it += NT) {
+            const int al = it / n, jj = it - al * n;
+            const G3 ph3 = phase_cart3(xA[al], ph, kk[jj].x, kk[jj].y);
+            const cpx<T> g0 = cmul(cis<T>(ph3.g), fs[jj]);
+            gA[0][al][jj] = g0;
+            gA[1][al][jj] = i2pi(ph3.d1, g0);
+            gA[2][al][jj] = i2pi(ph3.d2, g0);
+        }
+        __syncthreads();
+        if (active) {
+            for (int jj = 0; jj < n; ++jj) {
+                const T l1 = lag1[jj][t1];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const cpx<T> gv = gA[k][aL][jj];
+                    const cpx<T> h = {l1 * gv.re, l1 * gv.im};
+#pragma unroll
+                    for (int t2 = 0; t2 < Q; ++t2) crfma(acc[k][t2], lag2[jj][t2], h);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    const uint32_t mA = a0 + aL;
+    const XP xp = xA[aL];
+    const double rho = g.rho_scale * box_node(bp1, lB, zs[t1]);
+    cpx<T> *out = w + ((size_t)mA * ((size_t)1 << (2 * lB)) + mB) * (Q * Q) + t1 * Q;
+#pragma unroll
+    for (int t2 = 0; t2 < Q; ++t2) {
+        double st, ct;
+        sincospi(2.0 * box_node(bp2, lB, zs[t2]), &st, &ct);
+        const G3 gr = phase_dir3(xp, ph, ct, st);
+        const cpx<T> e = cis<T>(rho * gr.g);
+        const cpx<T> o0 = cmulc(acc[0][t2], e);
+        out[t2] = o0;
+        out[plane + t2] = csub(cmulc(acc[1][t2], e), i2pi(rho * gr.d1, o0));
+        out[2 * plane + t2] = csub(cmulc(acc[2][t2], e), i2pi(rho * gr.d2, o0));
+    }
+}
+
+// ===========================================================================
+// p-recursion (eq:alg2b) with derivatives, one workgroup per block (A_p, B),
+// the four outputs one after another:
+//   v   = Ep . in,       d v = Ep . (d in + 2 pi i dPhi_p . in)
+//   out = conj Er . K v, d out = conj Er . K d v - 2 pi i dPhi_r . out
+// ===========================================================================
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables tb, int level,
+                                                   const cpx<T> *__restrict__ win,
+                                                   cpx<T> *__restrict__ wout, size_t plane) {
+    constexpr int QQ = Q * Q;
+    __shared__ cpx<T> v[3][4 * QQ];
+    __shared__ cpx<T> W[3][2 * QQ];
+    __shared__ T Ms[2 * QQ];
+    __shared__ double rc[2 * Q], ctc[2 * Q], stc[2 * Q];
+    __shared__ double rb[Q], ctb[Q], stb[Q];
+    __shared__ G3 Gc[2 * Q], Gb[Q];
+
+    const int tid = threadIdx.x;
+    const int lB = g.L - level;
+    const size_t blk = blockIdx.x;
+    const size_t nBl = (size_t)1 << (2 * lB);
+    const uint32_t mB = (uint32_t)(blk & (nBl - 1));
+    const uint32_t mAp = (uint32_t)(blk >> (2 * lB));
+    int b1, b2, ap1, ap2;
+    morton_decode(mB, b1, b2);
+    morton_decode(mAp, ap1, ap2);
+
+    const T *Mg = pick_M<T>(tb);
+    for (int i = tid; i < 2 * QQ; i += NT) Ms[i] = Mg[i];
+    if (tid < 2 * Q) {
+        const int c = tid / Q, t = tid - c * Q;
+        const double z = tb.z[t];
+        rc[tid] = g.rho_scale * box_node(2 * b1 + c, lB + 1, z);
+        double s_, c_;
+        sincospi(2.0 * box_node(2 * b2 + c, lB + 1, z), &s_, &c_);
+        ctc[tid] = c_;
+        stc[tid] = s_;
+    } else if (tid >= 64 && tid < 64 + Q) {
+        const int t = tid - 64;
+        const double z = tb.z[t];
+        rb[t] = g.rho_scale * box_node(b1, lB, z);
+        double s_, c_;
+        sincospi(2.0 * box_node(b2, lB, z), &s_, &c_);
+        ctb[t] = c_;
+        stb[t] = s_;
+    }
+    __syncthreads();
+    const cpx<T> *src = win + blk * (4 * QQ);
+    for (int j = 0; j < 4; ++j) {
+        const int a1 = 2 * ap1 + (j >> 1), a2 = 2 * ap2 + (j & 1);
+        const XP xp = make_xp(ph, box_centre(a1, level), box_centre(a2, level));
+        if (tid < 2 * Q) Gc[tid] = phase_dir3(xp, ph, ctc[tid], stc[tid]);
+        else if (tid >= 64 && tid < 64 + Q) Gb[tid - 64] = phase_dir3(xp, ph, ctb[tid - 64], stb[tid - 64]);
+        __syncthreads();
+        for (int i = tid; i < 4 * QQ; i += NT) {
+            const int c = i / QQ, t = i - c * QQ;
+            const int c1 = c >> 1, c2 = c & 1;
+            const int tp1 = t / Q, tp2 = t - tp1 * Q;
+            const double rho = rc[c1 * Q + tp1];
+            const G3 gg = Gc[c2 * Q + tp2];
+            const cpx<T> e = cis<T>(rho * gg.g);
+            const cpx<T> in0 = src[i];
+            v[0][i] = cmul(e, in0);
+            v[1][i] = cmul(e, cadd(src[plane + i], i2pi(rho * gg.d1, in0)));
+            v[2][i] = cmul(e, cadd(src[2 * plane + i], i2pi(rho * gg.d2, in0)));
+        }
+        __syncthreads();
+        for (int i = tid; i < 3 * 2 * QQ; i += NT) {
+            const int k = i / (2 * QQ), ii = i - k * 2 * QQ;
+            const int c1 = ii / QQ, rr = ii - c1 * QQ;
+            const int tp1 = rr / Q, t2 = rr - tp1 * Q;
+            cpx<T> acc = {(T)0, (T)0};
+#pragma unroll
+            for (int c2 = 0; c2 < 2; ++c2) {
+                const cpx<T> *vv = v[k] + (2 * c1 + c2) * QQ + tp1 * Q;
+                const T *m = Ms + c2 * QQ + t2 * Q;
+#pragma unroll
+                for (int tp2 = 0; tp2 < Q; ++tp2) crfma(acc, m[tp2], vv[tp2]);
+            }
+            W[k][ii] = acc;
+        }
+        __syncthreads();
+        cpx<T> *dst = wout + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
+        for (int i = tid; i < QQ; i += NT) {
+            const int t1 = i / Q, t2 = i - t1 * Q;
+            cpx<T> o[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                cpx<T> acc = {(T)0, (T)0};
+#pragma unroll
+                for (int c1 = 0; c1 < 2; ++c1) {
+                    const T *m = Ms + c1 * QQ + t1 * Q;
+#pragma unroll
+                    for (int tp1 = 0; tp1 < Q; ++tp1) crfma(acc, m[tp1], W[k][c1 * QQ + tp1 * Q + t2]);
+                }
+                o[k] = acc;
+            }
+            const G3 gg = Gb[t2];
+            const cpx<T> e = cis<T>(rb[t1] * gg.g);
+            const cpx<T> o0 = cmulc(o[0], e);
+            dst[i] = o0;
+            dst[plane + i] = csub(cmulc(o[1], e), i2pi(rb[t1] * gg.d1, o0));
+            dst[2 * plane + i] = csub(cmulc(o[2], e), i2pi(rb[t1] * gg.d2, o0));
+        }
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
+// switch (eq:alg2m) with derivatives, in place on three planes:
+//   out   = sum_s E[t,s] in[s]
+//   d out = sum_s E[t,s] (d in[s] + 2 pi i rho(s1) dG(x_t, theta_s2) in[s])
+// With the same node symmetry as the forward switch; the derivative term
+// uses the weighted plane in'(s) = rho(s1) in(s).
+// ===========================================================================
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k_switch_tan(Geom g, PhaseDev ph, Tables tb, cpx<T> *__restrict__ w,
+                                                   size_t plane) {
+    constexpr int QQ = Q * Q;
+    constexpr int H = Q / 2;
+    constexpr int HH = H > 0 ? H : 1;
+    constexpr int PPB = NT / QQ;
+    __shared__ cpx<T> Sx[PPB][4][Q][HH];
+    __shared__ cpx<T> Dx[PPB][4][Q][HH];
+    __shared__ cpx<T> Mid[PPB][4][Q];
+    __shared__ double cth[PPB][Q], sth[PPB][Q], rhos[PPB][Q];
+    __shared__ double rho0[PPB], hz[PPB][HH];
+
+    const int tid = threadIdx.x;
+    const int pl = tid / QQ, t = tid - pl * QQ;
+    const size_t npairs = (size_t)1 << (2 * g.L);
+    const size_t pair = (size_t)blockIdx.x * PPB + pl;
+    const bool active = (pl < PPB) && (pair < npairs);
+    const int lA = g.lm, lB = g.L - g.lm;
+    const size_t nBl = (size_t)1 << (2 * lB);
+    const uint32_t mB = active ? (uint32_t)(pair & (nBl - 1)) : 0;
+    const uint32_t mA = active ? (uint32_t)(pair >> (2 * lB)) : 0;
+    int b1, b2, a1, a2;
+    morton_decode(mB, b1, b2);
+    morton_decode(mA, a1, a2);
+    const int t1 = t / Q, t2 = t - t1 * Q;
+    cpx<T> *wp = w + pair * QQ;
+
+    if (active) {
+        if (t < Q) {
+            double s_, c_;
+            sincospi(2.0 * box_node(b2, lB, tb.z[t]), &s_, &c_);
+            cth[pl][t] = c_;
+            sth[pl][t] = s_;
+            rhos[pl][t] = g.rho_scale * box_node(b1, lB, tb.z[t]);
+        } else if (t == Q) {
+            rho0[pl] = g.rho_scale * box_centre(b1, lB);
+        } else if (t > Q && t <= Q + H) {
+            hz[pl][t - Q - 1] = g.rho_scale * ldexp(tb.z[t - Q - 1], -lB);
+        }
+    }
+    __syncthreads();
+    if (active) {
+        // planes 0, 1, 2 and the weighted primal rho(s1) in0(s); thread (t1, t2): t1 plays j
+        if (t1 < H) {
+            const double ra = rhos[pl][t1], rbv = rhos[pl][Q - 1 - t1];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const size_t off = (k < 3 ? k : 0) * plane;
+                cpx<T> a = wp[off + t1 * Q + t2], b = wp[off + (Q - 1 - t1) * Q + t2];
+                if (k == 3) {
+                    a = {(T)(ra * a.re), (T)(ra * a.im)};
+                    b = {(T)(rbv * b.re), (T)(rbv * b.im)};
+                }
+                Sx[pl][k][t2][t1] = cadd(a, b);
+                Dx[pl][k][t2][t1] = csub(a, b);
+            }
+        } else if ((Q & 1) && t1 == H) {
+            const double rm = rhos[pl][H];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Mid[pl][k][t2] = wp[k * plane + H * Q + t2];
+            const cpx<T> a = wp[H * Q + t2];
+            Mid[pl][3][t2] = {(T)(rm * a.re), (T)(rm * a.im)};
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    const XP xp = make_xp(ph, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]));
+    const double r0 = rho0[pl];
+    cpx<T> acc[3] = {{(T)0, (T)0}, {(T)0, (T)0}, {(T)0, (T)0}};
+#pragma unroll 1
+    for (int s2 = 0; s2 < Q; ++s2) {
+        const G3 G = phase_dir3(xp, ph, cth[pl][s2], sth[pl][s2]);
+        const cpx<T> base = cis<T>(r0 * G.g);
+        cpx<T> d[HH];
+#pragma unroll
+        for (int j = 0; j < H; ++j) d[j] = cis<T>(hz[pl][j] * G.g);
+        cpx<T> inner[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            cpx<T> in = (Q & 1) ? Mid[pl][k][s2] : cpx<T>{(T)0, (T)0};
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const cpx<T> S = Sx[pl][k][s2][j], D = Dx[pl][k][s2][j];
+                in.re = fma(d[j].re, S.re, fma(-d[j].im, D.im, in.re));
+                in.im = fma(d[j].re, S.im, fma(d[j].im, D.re, in.im));
+            }
+            inner[k] = in;
+        }
+        cfma(acc[0], base, inner[0]);
+        cfma(acc[1], base, cadd(inner[1], i2pi(G.d1, inner[3])));
+        cfma(acc[2], base, cadd(inner[2], i2pi(G.d2, inner[3])));
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) wp[k * plane + t] = acc[k];
+}
+
+// ===========================================================================
+// x-recursion (eq:alg2c) with derivatives, one workgroup per block:
+//   v   = conj Ep . in,  d v = conj Ep . (d in - 2 pi i dPhi_p . in)
+//   out = sum_c Er_c . z_c, z_c = K_A v_c;  d out = sum_c Er_c . (d z_c + 2 pi i dPhi_r,c . z_c)
+// ===========================================================================
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables tb, int level,
+                                                   const cpx<T> *__restrict__ win,
+                                                   cpx<T> *__restrict__ wout, size_t plane) {
+    constexpr int QQ = Q * Q;
+    __shared__ cpx<T> v[3][4 * QQ];
+    __shared__ cpx<T> Y[3][4 * QQ];
+    __shared__ T Ms[2 * QQ];
+    __shared__ double sx1[Q], cx1[Q], sx2[Q], cx2[Q];
+    __shared__ double r0c[2], ct0[2], st0[2];
+
+    const int tid = threadIdx.x;
+    const int lB = g.L - level;
+    const size_t blk = blockIdx.x;
+    const size_t nBl = (size_t)1 << (2 * lB);
+    const uint32_t mB = (uint32_t)(blk & (nBl - 1));
+    const uint32_t mAp = (uint32_t)(blk >> (2 * lB));
+    int b1, b2, ap1, ap2;
+    morton_decode(mB, b1, b2);
+    morton_decode(mAp, ap1, ap2);
+    const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
+
+    const T *Mg = pick_M<T>(tb);
+    for (int i = tid; i < 2 * QQ; i += NT) Ms[i] = Mg[i];
+    if (tid < 2) {
+        r0c[tid] = g.rho_scale * box_centre(2 * b1 + tid, lB + 1);
+        double s_, c_;
+        sincospi(2.0 * box_centre(2 * b2 + tid, lB + 1), &s_, &c_);
+        ct0[tid] = c_;
+        st0[tid] = s_;
+    } else if (tid >= 64 && tid < 64 + Q) {
+        const int t = tid - 64;
+        double s_ = 0, c_ = 1;
+        if (ell) sincospi(2.0 * box_node(ap1, level - 1, tb.z[t]), &s_, &c_);
+        sx1[t] = s_;
+        cx1[t] = c_;
+    } else if (tid >= 128 && tid < 128 + Q) {
+        const int t = tid - 128;
+        double s_ = 0, c_ = 1;
+        if (ell) sincospi(2.0 * box_node(ap2, level - 1, tb.z[t]), &s_, &c_);
+        sx2[t] = s_;
+        cx2[t] = c_;
+    }
+    __syncthreads();
+    const cpx<T> *src = win + blk * (4 * QQ);
+    for (int i = tid; i < 2 * QQ; i += NT) {
+        const int c2 = i / QQ, tp = i - c2 * QQ;
+        const int tp1 = tp / Q, tp2 = tp - tp1 * Q;
+        const XP xp = make_xp_sc(ph, box_node(ap1, level - 1, tb.z[tp1]), box_node(ap2, level - 1, tb.z[tp2]),
+                                 sx1[tp1], cx1[tp1], sx2[tp2], cx2[tp2]);
+        const G3 G = phase_dir3(xp, ph, ct0[c2], st0[c2]);
+#pragma unroll
+        for (int c1 = 0; c1 < 2; ++c1) {
+            const int c = 2 * c1 + c2;
+            const double rho = r0c[c1];
+            const cpx<T> e = cis<T>(rho * G.g);
+            const cpx<T> in0 = src[c * QQ + tp];
+            v[0][c * QQ + tp] = cmulc(in0, e);
+            v[1][c * QQ + tp] = cmulc(csub(src[plane + c * QQ + tp], i2pi(rho * G.d1, in0)), e);
+            v[2][c * QQ + tp] = cmulc(csub(src[2 * plane + c * QQ + tp], i2pi(rho * G.d2, in0)), e);
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < 4; ++j) {
+        const int j1 = j >> 1, j2 = j & 1;
+        const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
+        if (tid < Q) {
+            double s_ = 0, c_ = 1;
+            if (ell) sincospi(2.0 * box_node(a1, level, tb.z[tid]), &s_, &c_);
+            sx1[tid] = s_;
+            cx1[tid] = c_;
+        } else if (tid >= 64 && tid < 64 + Q) {
+            const int t = tid - 64;
+            double s_ = 0, c_ = 1;
+            if (ell) sincospi(2.0 * box_node(a2, level, tb.z[t]), &s_, &c_);
+            sx2[t] = s_;
+            cx2[t] = c_;
+        }
+        for (int i = tid; i < 3 * 4 * QQ; i += NT) {
+            const int k = i / (4 * QQ), ii = i - k * 4 * QQ;
+            const int c = ii / QQ, r = ii - c * QQ;
+            const int tp1 = r / Q, t2 = r - tp1 * Q;
+            const cpx<T> *vv = v[k] + c * QQ + tp1 * Q;
+            const T *m = Ms + j2 * QQ + t2;
+            cpx<T> acc = {(T)0, (T)0};
+#pragma unroll
+            for (int tp2 = 0; tp2 < Q; ++tp2) crfma(acc, m[tp2 * Q], vv[tp2]);
+            Y[k][ii] = acc;
+        }
+        __syncthreads();
+        cpx<T> *dst = wout + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
+        for (int i = tid; i < QQ; i += NT) {
+            const int t1 = i / Q, t2 = i - t1 * Q;
+            const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[t2]), sx1[t1],
+                                     cx1[t1], sx2[t2], cx2[t2]);
+            const G3 G0 = phase_dir3(xp, ph, ct0[0], st0[0]);
+            const G3 G1 = phase_dir3(xp, ph, ct0[1], st0[1]);
+            cpx<T> out[3] = {{(T)0, (T)0}, {(T)0, (T)0}, {(T)0, (T)0}};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int c1 = c >> 1, c2 = c & 1;
+                const T *m = Ms + j1 * QQ + t1;
+                cpx<T> z[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    cpx<T> acc = {(T)0, (T)0};
+#pragma unroll
+                    for (int tp1 = 0; tp1 < Q; ++tp1) crfma(acc, m[tp1 * Q], Y[k][c * QQ + tp1 * Q + t2]);
+                    z[k] = acc;
+                }
+                const G3 &G = c2 ? G1 : G0;
+                const double rho = r0c[c1];
+                const cpx<T> e = cis<T>(rho * G.g);
+                cfma(out[0], e, z[0]);
+                cfma(out[1], e, cadd(z[1], i2pi(rho * G.d1, z[0])));
+                cfma(out[2], e, cadd(z[2], i2pi(rho * G.d2, z[0])));
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dst[k * plane + i] = out[k];
+        }
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
+// termination (eq:alg2d) with derivatives:
+//   v = conj Et . delta, d v = conj Et . (d delta - 2 pi i dPhi_t . delta)
+//   u = sum_B Ex . U,   U = T_x v;   d u = sum_B Ex . (d U + 2 pi i dPhi_x . U)
+// ===========================================================================
+template <typename T, int Q>
+constexpr int bch3() {
+    return bch<T, Q>() / 3 < 1 ? 1 : bch<T, Q>() / 3;
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k_term_tan(Geom g, PhaseDev ph, Tables tb, const cpx<T> *__restrict__ win,
+                                                 size_t plane, cpx<T> *u0, cpx<T> *u1, cpx<T> *u2) {
+    constexpr int QQ = Q * Q;
+    constexpr int BC = bch3<T, Q>();
+    __shared__ cpx<T> v[3][BC * QQ];
+    __shared__ cpx<T> Y[3][BC * Q * 8];
+    __shared__ cpx<T> red[NT];
+    __shared__ double sx1[Q], cx1[Q], sx2[Q], cx2[Q];
+    __shared__ double r0b[BC], ctb[BC], stb[BC];
+
+    const int tid = threadIdx.x;
+    const int s = g.s;
+    const int m = 1 << s, np = m * m;
+    const int nBt = 1 << (2 * s);
+    const int lA = g.L - s;
+    const uint32_t mA = blockIdx.x;
+    int a1, a2;
+    morton_decode(mA, a1, a2);
+    const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
+    const T *Tt = pick_T<T>(tb);
+
+    if (tid < Q) {
+        double s_ = 0, c_ = 1;
+        if (ell) sincospi(2.0 * box_node(a1, lA, tb.z[tid]), &s_, &c_);
+        sx1[tid] = s_;
+        cx1[tid] = c_;
+    } else if (tid >= 64 && tid < 64 + Q) {
+        const int t = tid - 64;
+        double s_ = 0, c_ = 1;
+        if (ell) sincospi(2.0 * box_node(a2, lA, tb.z[t]), &s_, &c_);
+        sx2[t] = s_;
+        cx2[t] = c_;
+    }
+    const int jp = tid % np;
+    const int j1 = jp / m, j2 = jp - j1 * m;
+    const XP xg = make_xp(ph, (double)(a1 * m + j1) / g.N, (double)(a2 * m + j2) / g.N);
+    cpx<T> uacc[3] = {{(T)0, (T)0}, {(T)0, (T)0}, {(T)0, (T)0}};
+
+    const cpx<T> *src = win + (size_t)mA * nBt * QQ;
+    for (int b0 = 0; b0 < nBt; b0 += BC) {
+        const int nb = min(BC, nBt - b0);
+        if (tid < nb) {
+            int bb1, bb2;
+            morton_decode((uint32_t)(b0 + tid), bb1, bb2);
+            r0b[tid] = g.rho_scale * box_centre(bb1, s);
+            double s_, c_;
+            sincospi(2.0 * box_centre(bb2, s), &s_, &c_);
+            ctb[tid] = c_;
+            stb[tid] = s_;
+        }
+        __syncthreads();
+        for (int i = tid; i < nb * QQ; i += NT) {
+            const int b = i / QQ, t = i - b * QQ;
+            const int t1 = t / Q, t2 = t - t1 * Q;
+            const XP xp = make_xp_sc(ph, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]), sx1[t1], cx1[t1],
+                                     sx2[t2], cx2[t2]);
+            const G3 G = phase_dir3(xp, ph, ctb[b], stb[b]);
+            const double rho = r0b[b];
+            const cpx<T> e = cis<T>(rho * G.g);
+            const size_t o = (size_t)(b0 + b) * QQ + t;
+            const cpx<T> d0 = src[o];
+            v[0][i] = cmulc(d0, e);
+            v[1][i] = cmulc(csub(src[plane + o], i2pi(rho * G.d1, d0)), e);
+            v[2][i] = cmulc(csub(src[2 * plane + o], i2pi(rho * G.d2, d0)), e);
+        }
+        __syncthreads();
+        for (int i = tid; i < 3 * nb * Q * m; i += NT) {
+            const int k = i / (nb * Q * m), ii = i - k * nb * Q * m;
+            const int b = ii / (Q * m), r = ii - b * (Q * m);
+            const int t1 = r / m, jj2 = r - t1 * m;
+            const cpx<T> *vv = v[k] + b * QQ + t1 * Q;
+            cpx<T> acc = {(T)0, (T)0};
+#pragma unroll
+            for (int t2 = 0; t2 < Q; ++t2) crfma(acc, Tt[jj2 * Q + t2], vv[t2]);
+            Y[k][ii] = acc;
+        }
+        __syncthreads();
+        for (int i = tid; i < nb * np; i += NT) {
+            const int b = i / np;
+            cpx<T> U[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                cpx<T> acc = {(T)0, (T)0};
+                const cpx<T> *yy = Y[k] + b * Q * m + j2;
+#pragma unroll
+                for (int t1 = 0; t1 < Q; ++t1) crfma(acc, Tt[j1 * Q + t1], yy[t1 * m]);
+                U[k] = acc;
+            }
+            const G3 G = phase_dir3(xg, ph, ctb[b], stb[b]);
+            const double rho = r0b[b];
+            const cpx<T> e = cis<T>(rho * G.g);
+            cfma(uacc[0], e, U[0]);
+            cfma(uacc[1], e, cadd(U[1], i2pi(rho * G.d1, U[0])));
+            cfma(uacc[2], e, cadd(U[2], i2pi(rho * G.d2, U[0])));
+        }
+        __syncthreads();
+    }
+    cpx<T> *const dst[3] = {u0, u1, u2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        red[tid] = uacc[k];
+        __syncthreads();
+        if (tid < np && dst[k] != nullptr) {
+            cpx<T> sum = red[tid];
+            for (int kk = tid + np; kk < NT; kk += np) sum = cadd(sum, red[kk]);
+            dst[k][(size_t)(a1 * m + j1) * g.N + (a2 * m + j2)] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+#define FIO_DISPATCH_QT(q, MACRO)  \
+    switch (q) {                   \
+        case 3: MACRO(3); break;   \
+        case 4: MACRO(4); break;   \
+        case 5: MACRO(5); break;   \
+        case 6: MACRO(6); break;   \
+        case 7: MACRO(7); break;   \
+        case 8: MACRO(8); break;   \
+        case 9: MACRO(9); break;   \
+        case 10: MACRO(10); break; \
+        case 11: MACRO(11); break; \
+        case 12: MACRO(12); break; \
+        default: return hipErrorInvalidValue; \
+    }
+
+bool tangent_supported_q(int q) { return q >= QMIN && q <= 12; }
+
+template <typename T>
+static hipError_t tan_t(int step, const Geom &g, const PhaseDev &ph, const Tables &tb, const Sources &src,
+                        int level, const void *in, void *out, size_t plane, void *u1, void *u2,
+                        hipStream_t st) {
+    if (step == 0) {
+        const unsigned nB = 1u << (2 * (g.L - g.s));
+        const int nA = 1 << (2 * g.s);
+#define L_IT(Q)                                                                                          \
+    {                                                                                                    \
+        constexpr int ACH = (NT / Q) < 64 ? (NT / Q) : 64;                                               \
+        hipLaunchKernelGGL((k_init_tan<T, Q>), dim3(nB, (nA + ACH - 1) / ACH), dim3(NT), 0, st, g, ph, tb, \
+                           src, (const cpx<T> *)in, (cpx<T> *)out, plane);                               \
+    }
+        FIO_DISPATCH_QT(g.q, L_IT)
+#undef L_IT
+    } else if (step == 1 || step == 3) {
+        const unsigned nblk = 1u << (2 * g.L - 2);
+#define L_LT(Q)                                                                                          \
+    if (step == 1)                                                                                       \
+        hipLaunchKernelGGL((k_plevel_tan<T, Q>), dim3(nblk), dim3(NT), 0, st, g, ph, tb, level,          \
+                           (const cpx<T> *)in, (cpx<T> *)out, plane);                                    \
+    else                                                                                                 \
+        hipLaunchKernelGGL((k_xlevel_tan<T, Q>), dim3(nblk), dim3(NT), 0, st, g, ph, tb, level,          \
+                           (const cpx<T> *)in, (cpx<T> *)out, plane);
+        FIO_DISPATCH_QT(g.q, L_LT)
+#undef L_LT
+    } else if (step == 2) {
+        const size_t npairs = (size_t)1 << (2 * g.L);
+#define L_ST(Q)                                                                                          \
+    {                                                                                                    \
+        constexpr int PPB = NT / (Q * Q);                                                                \
+        hipLaunchKernelGGL((k_switch_tan<T, Q>), dim3((unsigned)((npairs + PPB - 1) / PPB)), dim3(NT), 0, \
+                           st, g, ph, tb, (cpx<T> *)out, plane);                                         \
+    }
+        FIO_DISPATCH_QT(g.q, L_ST)
+#undef L_ST
+    } else {
+        const unsigned nA = 1u << (2 * (g.L - g.s));
+#define L_TT(Q)                                                                                          \
+    hipLaunchKernelGGL((k_term_tan<T, Q>), dim3(nA), dim3(NT), 0, st, g, ph, tb, (const cpx<T> *)in,     \
+                       plane, (cpx<T> *)out, (cpx<T> *)u1, (cpx<T> *)u2);
+        FIO_DISPATCH_QT(g.q, L_TT)
+#undef L_TT
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tangent_step(int dtype, int step, const Geom &g, const PhaseDev &ph, const Tables &tb,
+                               const Sources &src, int level, const void *in, void *out, size_t plane,
+                               void *u1, void *u2, hipStream_t st) {
+    return dtype == FIO_C128 ? tan_t<double>(step, g, ph, tb, src, level, in, out, plane, u1, u2, st)
+                             : tan_t<float>(step, g, ph, tb, src, level, in, out, plane, u1, u2, st);
+}
+
+}  // namespace fio

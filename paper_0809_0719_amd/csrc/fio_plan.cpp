@@ -1,6 +1,7 @@
 // Host side of the C ABI: argument validation, the plan (trees of Sec. 4
 // step 1, interpolation tables, workspace), and the level schedule that
-// drives the kernels of fio_kernels_fwd.hip and fio_kernels_adj.hip.
+// drives the kernels of fio_kernels_fwd.hip, fio_kernels_adj.hip,
+// fio_kernels_mfma.hip and fio_kernels_tan.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -90,6 +91,7 @@ struct fio_plan_s {
     size_t plane = 0;        // complex values per plane = N^2 q^2
     size_t total_bytes = 0;  // all device memory of the plan
     void *w0 = nullptr, *w1 = nullptr;
+    void *t0 = nullptr, *t1 = nullptr;  // tangent workspace (3 planes each), when nrhs_max < 3
     void *dtab = nullptr;    // tables
     int32_t *d_idx = nullptr, *d_off = nullptr;
     double2 *d_p = nullptr;
@@ -109,6 +111,8 @@ void free_plan(fio_plan_s *p) {
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     (void)hipFree(p->w0);
     (void)hipFree(p->w1);
+    (void)hipFree(p->t0);
+    (void)hipFree(p->t1);
     (void)hipFree(p->dtab);
     (void)hipFree(p->d_idx);
     (void)hipFree(p->d_off);
@@ -465,6 +469,63 @@ static int run_adjoint(fio_plan_t p, const void *u, void *f, int nr, hipStream_t
         e = launch_init_adj(p->dtype, p->geom, ph, p->tb, src, a + r * p->wbytes, (char *)f + r * fstep, st);
     }
     if (e != hipSuccess) return hip_fail(e, "initialisation^H launch");
+    return FIO_OK;
+}
+
+// Primal and the two phase tangents of one right-hand side through the
+// whole pass (kernels of fio_kernels_tan.hip).
+static int run_tangent(fio_plan_t p, const void *f, void *u, void *d1, void *d2, hipStream_t st) {
+    const PhaseDev ph = to_dev(&p->phase);
+    Sources src{p->d_idx, p->d_p, p->d_off};
+    char *a = (char *)(p->nrhs_max >= 3 ? p->w0 : p->t0), *b = (char *)(p->nrhs_max >= 3 ? p->w1 : p->t1);
+    Timed tm(p, FIO_K_TANGENT, st);
+    hipError_t e = launch_tangent_step(p->dtype, 0, p->geom, ph, p->tb, src, 0, f, a, p->plane, nullptr,
+                                       nullptr, st);
+    for (int l = p->s + 1; l <= p->lm && e == hipSuccess; ++l) {
+        e = launch_tangent_step(p->dtype, 1, p->geom, ph, p->tb, src, l, a, b, p->plane, nullptr, nullptr, st);
+        std::swap(a, b);
+    }
+    if (e == hipSuccess)
+        e = launch_tangent_step(p->dtype, 2, p->geom, ph, p->tb, src, p->lm, a, a, p->plane, nullptr, nullptr,
+                                st);
+    for (int l = p->lm + 1; l <= p->L - p->s && e == hipSuccess; ++l) {
+        e = launch_tangent_step(p->dtype, 3, p->geom, ph, p->tb, src, l, a, b, p->plane, nullptr, nullptr, st);
+        std::swap(a, b);
+    }
+    if (e == hipSuccess)
+        e = launch_tangent_step(p->dtype, 4, p->geom, ph, p->tb, src, 0, a, u, p->plane, d1, d2, st);
+    if (e != hipSuccess) return hip_fail(e, "tangent launch");
+    return FIO_OK;
+}
+
+int fio_apply_dphase(fio_plan_t plan, const void *f, void *u, void *du_da1, void *du_da2, int nrhs,
+                     void *stream) {
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!f || !du_da1 || !du_da2) return fail(FIO_EINVAL, "f, du_da1 and du_da2 must be non-NULL device pointers");
+    if (nrhs < 1) return fail(FIO_EINVAL, "nrhs must be >= 1 (got %d)", nrhs);
+    if (!tangent_supported_q(plan->q)) return fail(FIO_EINVAL, "phase derivatives need q <= 12 (got %d)", plan->q);
+    if (f == u || f == du_da1 || f == du_da2 || du_da1 == du_da2 || (u && (u == du_da1 || u == du_da2)))
+        return fail(FIO_EINVAL, "f, u, du_da1 and du_da2 must not overlap");
+    if ((rc = set_device(plan))) return rc;
+    if (plan->nrhs_max < 3 && !plan->t0) {
+        size_t tot = plan->total_bytes;
+        if ((rc = dmalloc(&plan->t0, 3 * plan->wbytes, &tot, "tangent weights 0")) ||
+            (rc = dmalloc(&plan->t1, 3 * plan->wbytes, &tot, "tangent weights 1"))) {
+            (void)hipFree(plan->t0);
+            plan->t0 = nullptr;
+            return rc;
+        }
+        plan->total_bytes = tot;
+    }
+    const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
+    hipStream_t st = (hipStream_t)stream;
+    for (int r = 0; r < nrhs; ++r) {
+        rc = run_tangent(plan, (const char *)f + r * step, u ? (char *)u + r * step : nullptr,
+                         (char *)du_da1 + r * step, (char *)du_da2 + r * step, st);
+        if (rc) return rc;
+    }
     return FIO_OK;
 }
 
