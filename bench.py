@@ -49,7 +49,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 EXP, PHS, CRMAC, CMUL = 12, 9, 2, 4
 
 
-def lane_ops(kind: str, N: int, q: int, s: int, nrhs: int, rc_switch: int = 8, rc_switch_adj: int = 2) -> float:
+def lane_ops(kind: str, N: int, q: int, s: int, nrhs: int, rc_switch: int = 8, rc_switch_adj: int = 4) -> float:
     n2 = float(N) * N
     h = q // 2
     m = 1 << s
@@ -62,7 +62,10 @@ def lane_ops(kind: str, N: int, q: int, s: int, nrhs: int, rc_switch: int = 8, r
         rc = 1 if nrhs == 1 else (rc_switch if kind == "switch" else rc_switch_adj)
         chunks = -(-nrhs // rc)
         shared = q ** 3 * (PHS + (1 + h) * EXP)
-        per_rhs = q ** 3 * (4 * h + 4)
+        # forward: h paired updates (4 FMA) and one complex multiply-add per
+        # (t, s2); adjoint: one conjugate product, h pairs of real-by-complex
+        # multiply-adds and, for odd q, the middle row's addition
+        per_rhs = q ** 3 * (4 * h + 4 + (2 * (q & 1) if kind == "switch_adj" else 0))
         return n2 * (chunks * shared + nrhs * per_rhs)
     if kind in ("init", "init_adj"):
         # per (A, source): phase + exponential + product + q^2 + q multiply-adds;

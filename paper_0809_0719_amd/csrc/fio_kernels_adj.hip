@@ -272,22 +272,34 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
 }
 
 // switch^H at level lm, in place: delta_s <- sum_t conj E(x^A_t, p^B_s) delta_t.
-// Thread <-> (pair, s2) accumulates all q values of s1, using the same
-// rho0 + h_j symmetry as the forward switch; right-hand sides in chunks.
+// Thread <-> (pair, s2) owns the q outputs s1 of its column.  With
+// rho(s1) = rho0 + h_s1 and z_{q-1-j} = -z_j, the factor of (t, s) is
+// conj(base) conj(d_j) for s1 = j and conj(base) d_j for s1 = q-1-j, where
+// base = exp(2 pi i rho0 G), d_j = exp(2 pi i h_j G), G = G(x_t, theta_s2).
+// So per t the thread forms b = conj(base) delta_t once per right-hand side
+// and accumulates P_j = sum_t Re(d_j) b and Q_j = sum_t Im(d_j) b (4 FMA per
+// pair of outputs); at the end out_j = P_j - i Q_j, out_{q-1-j} = P_j + i Q_j.
+// The 1 + floor(q/2) exponentials of (t, s2) serve a chunk of RC right-hand
+// sides.  The inputs of the workgroup's pairs are staged through LDS one row
+// t1 at a time, double-buffered: the loads of row t1+1 are issued before the
+// arithmetic of row t1 and land in LDS after it.
 template <typename T, int Q, int RC, bool ONE>
 __global__ __launch_bounds__(NT) void k_switch_adj(Geom g, PhaseDev ph, Tables tb, cpx<T> *__restrict__ w,
                                                    int nrhs, size_t plane) {
     constexpr int QQ = Q * Q;
     constexpr int H = Q / 2;
     constexpr int HH = H > 0 ? H : 1;
-    constexpr int PPB = swadj_ppb<T, Q, RC>();
-    __shared__ cpx<T> dl[PPB][RC][QQ];
+    constexpr int PPB = NT / Q;
+    constexpr int ROW = PPB * RC * Q;             // staged values per row
+    constexpr int LPT = (ROW + NT - 1) / NT;      // of which each thread loads LPT
+    __shared__ cpx<T> rowbuf[2][RC][PPB][Q];
     __shared__ double sx[PPB][2][Q], cx[PPB][2][Q];
 
     const int tid = threadIdx.x;
     const int pl = tid / Q, s2 = tid - pl * Q;
     const size_t npairs = (size_t)1 << (2 * g.L);
-    const size_t pair = (size_t)blockIdx.x * PPB + pl;
+    const size_t pair0 = (size_t)blockIdx.x * PPB;
+    const size_t pair = pair0 + pl;
     const bool active = (pl < PPB) && (pair < npairs);
     const int lA = g.lm, lB = g.L - g.lm;
     const size_t nBl = (size_t)1 << (2 * lB);
@@ -317,58 +329,88 @@ __global__ __launch_bounds__(NT) void k_switch_adj(Geom g, PhaseDev ph, Tables t
 
     for (int q0 = 0; q0 < (ONE ? 1 : nrhs); q0 += RC) {
         const int nr = min(RC, nrhs - q0);
-        __syncthreads();
-        if (active)
-            for (int rc = 0; rc < nr; ++rc) {
-                const cpx<T> *wp = w + (size_t)(q0 + rc) * plane + pair * QQ;
-                for (int i = s2; i < QQ; i += Q) dl[pl][rc][i] = wp[i];
+        // staged element e = (rc * PPB + p) * Q + t2 of row t1
+        auto fetch = [&](int t1, cpx<T> (&v)[LPT]) {
+#pragma unroll
+            for (int k = 0; k < LPT; ++k) {
+                const int e = tid + k * NT;
+                const int rc = e / (PPB * Q), rem = e - rc * (PPB * Q);
+                const int p = rem / Q, t2 = rem - p * Q;
+                if (e < ROW && rc < nr && pair0 + p < npairs)
+                    v[k] = w[(size_t)(q0 + rc) * plane + (pair0 + p) * QQ + t1 * Q + t2];
             }
+        };
+        auto stash = [&](int buf, const cpx<T> (&v)[LPT]) {
+#pragma unroll
+            for (int k = 0; k < LPT; ++k) {
+                const int e = tid + k * NT;
+                const int rc = e / (PPB * Q), rem = e - rc * (PPB * Q);
+                const int p = rem / Q, t2 = rem - p * Q;
+                if (e < ROW) rowbuf[buf][rc][p][t2] = v[k];
+            }
+        };
+        cpx<T> pre[LPT];
+#pragma unroll
+        for (int k = 0; k < LPT; ++k) pre[k] = {(T)0, (T)0};
+        __syncthreads();  // the previous chunk's readers are done with rowbuf
+        fetch(0, pre);
+        stash(0, pre);
         __syncthreads();
-        if (!active) continue;
-        cpx<T> acc[RC][Q];
+
+        cpx<T> P[RC][HH], Qs[RC][HH], Mi[RC];
 #pragma unroll
-        for (int rc = 0; rc < RC; ++rc)
+        for (int rc = 0; rc < RC; ++rc) {
+            Mi[rc] = {(T)0, (T)0};
 #pragma unroll
-            for (int k = 0; k < Q; ++k) acc[rc][k] = {(T)0, (T)0};
+            for (int j = 0; j < HH; ++j) P[rc][j] = Qs[rc][j] = {(T)0, (T)0};
+        }
         for (int t1 = 0; t1 < Q; ++t1) {
-            for (int t2 = 0; t2 < Q; ++t2) {
-                const XP xp = make_xp_sc(ph, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]),
-                                         sx[pl][0][t1], cx[pl][0][t1], sx[pl][1][t2], cx[pl][1][t2]);
-                const double G = phase_dir(xp, ct, st);
-                const cpx<T> base = cis<T>(r0 * G);
-                cpx<T> d[HH];
+            const int buf = t1 & 1;
+            if (t1 + 1 < Q) fetch(t1 + 1, pre);
+            if (active) {
+                for (int t2 = 0; t2 < Q; ++t2) {
+                    const XP xp = make_xp_sc(ph, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]),
+                                             sx[pl][0][t1], cx[pl][0][t1], sx[pl][1][t2], cx[pl][1][t2]);
+                    const double G = phase_dir(xp, ct, st);
+                    const cpx<T> base = cis<T>(r0 * G);
+                    cpx<T> d[HH];
 #pragma unroll
-                for (int j = 0; j < H; ++j) d[j] = cis<T>(hz[j] * G);
+                    for (int j = 0; j < H; ++j) d[j] = cis<T>(hz[j] * G);
 #pragma unroll
-                for (int rc = 0; rc < RC; ++rc) {
-                    if (rc < nr) {
-                        // b = conj(exp(2 pi i r0 G)) delta_t
-                        const cpx<T> bb = cmulc(dl[pl][rc][t1 * Q + t2], base);
-                        if (Q & 1) {
-                            acc[rc][H].re += bb.re;
-                            acc[rc][H].im += bb.im;
-                        }
+                    for (int rc = 0; rc < RC; ++rc) {
+                        if (rc < nr) {
+                            const cpx<T> bb = cmulc(rowbuf[buf][rc][pl][t2], base);
+                            if (Q & 1) {
+                                Mi[rc].re += bb.re;
+                                Mi[rc].im += bb.im;
+                            }
 #pragma unroll
-                        for (int j = 0; j < H; ++j) {
-                            // conj(d) b -> s1 = j ; d b -> s1 = q-1-j
-                            const T pr = d[j].re * bb.re, pi = d[j].re * bb.im;
-                            const T qr = d[j].im * bb.im, qi = d[j].im * bb.re;
-                            acc[rc][j].re += pr + qr;
-                            acc[rc][j].im += pi - qi;
-                            acc[rc][Q - 1 - j].re += pr - qr;
-                            acc[rc][Q - 1 - j].im += pi + qi;
+                            for (int j = 0; j < H; ++j) {
+                                crfma(P[rc][j], d[j].re, bb);
+                                crfma(Qs[rc][j], d[j].im, bb);
+                            }
                         }
                     }
                 }
             }
+            if (t1 + 1 < Q) stash(buf ^ 1, pre);
+            __syncthreads();
         }
+        // every read of this chunk happened before the barrier above
+        if (active) {
 #pragma unroll
-        for (int rc = 0; rc < RC; ++rc)
-            if (rc < nr) {
-                cpx<T> *wp = w + (size_t)(q0 + rc) * plane + pair * QQ;
+            for (int rc = 0; rc < RC; ++rc)
+                if (rc < nr) {
+                    cpx<T> *wp = w + (size_t)(q0 + rc) * plane + pair * QQ;
 #pragma unroll
-                for (int k = 0; k < Q; ++k) wp[k * Q + s2] = acc[rc][k];
-            }
+                    for (int j = 0; j < H; ++j) {
+                        const cpx<T> p = P[rc][j], qq = Qs[rc][j];
+                        wp[j * Q + s2] = {p.re + qq.im, p.im - qq.re};
+                        wp[(Q - 1 - j) * Q + s2] = {p.re - qq.im, p.im + qq.re};
+                    }
+                    if (Q & 1) wp[H * Q + s2] = Mi[rc];
+                }
+        }
     }
 }
 
@@ -622,14 +664,13 @@ static hipError_t switch_adj_t(const Geom &g, const PhaseDev &ph, const Tables &
     const size_t npairs = (size_t)1 << (2 * g.L);
 #define L_SWA(Q)                                                                                     \
     {                                                                                                \
+        constexpr int PPB = NT / Q;                                                                  \
         if (nrhs == 1) {                                                                             \
-            constexpr int PPB = swadj_ppb<T, Q, 1>();                                                \
             const unsigned nblk = (unsigned)((npairs + PPB - 1) / PPB);                              \
             hipLaunchKernelGGL((k_switch_adj<T, Q, 1, true>), dim3(nblk), dim3(NT), 0, st, g, ph, tb,\
                                (cpx<T> *)w, nrhs, plane);                                            \
         } else {                                                                                     \
             constexpr int RC = swadj_rc<T>();                                                        \
-            constexpr int PPB = swadj_ppb<T, Q, RC>();                                               \
             const unsigned nblk = (unsigned)((npairs + PPB - 1) / PPB);                              \
             hipLaunchKernelGGL((k_switch_adj<T, Q, RC, false>), dim3(nblk), dim3(NT), 0, st, g, ph,  \
                                tb,                                                                   \

@@ -75,13 +75,7 @@ template <typename T>
 constexpr int switch_rc() { return sizeof(T) == 4 ? 8 : 4; }
 
 template <typename T>
-constexpr int swadj_rc() { return sizeof(T) == 4 ? 2 : 1; }
-
-template <typename T, int Q, int RC>
-constexpr int swadj_ppb() {
-    constexpr int byL = 32768 / (Q * Q * RC * (int)sizeof(cpx<T>));
-    return byL < (NT / Q) ? byL : (NT / Q);
-}
+constexpr int swadj_rc() { return sizeof(T) == 4 ? 4 : 2; }
 
 
 #define FIO_DISPATCH_Q(q, MACRO) \
