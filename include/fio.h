@@ -207,7 +207,8 @@ int fio_debug_stage(fio_plan_t plan, const void *f, int stage, void *weights, vo
 #define FIO_K_PLEVEL_ADJ  8
 #define FIO_K_INIT_ADJ    9
 #define FIO_K_TANGENT    10  /* every kernel of fio_apply_dphase */
-#define FIO_KERNEL_KINDS 11
+#define FIO_K_TABLES     11  /* kernel-value table, remade after a phase change */
+#define FIO_KERNEL_KINDS 12
 
 int fio_profile_enable(fio_plan_t plan, int enable);
 int fio_profile_read(fio_plan_t plan, double *ms, int64_t *launches, int n);

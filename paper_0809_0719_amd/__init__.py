@@ -49,7 +49,7 @@ EXPORTED_SYMBOLS = (
 # kernel kinds of fio_profile_read (FIO_K_* in include/fio.h)
 KERNEL_KINDS = ("init", "plevel", "switch", "xlevel", "term",
                 "term_adj", "xlevel_adj", "switch_adj", "plevel_adj", "init_adj",
-                "tangent")
+                "tangent", "tables")
 
 
 def library_path() -> str:

@@ -72,6 +72,25 @@ bool mfma_supported_q(int q);
 hipError_t launch_plevel_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
                               const void *w_in, void *w_out, int nrhs, size_t plane, hipStream_t st);
 
+// Initialisation and its adjoint on the matrix cores (fio_kernels_init.hip),
+// complex64, s = 3, q <= 9.  They read two tables in sorted source order:
+// ktab (N^2 rows of init_mfma_ktab_row(q) floats, the Lagrange products; made
+// once per plan by launch_init_tables) and etab (N^2 rows of 64 complex64,
+// E(x0(A), k); made by launch_init_etab whenever the phase changes).  The
+// forward gathers the `nrhs` right-hand sides (f planes N^2 apart) into
+// sorted order in `fsorted` (nrhs N^2 complex64) first; weights are planes
+// `plane` apart.
+bool init_mfma_supported(int q, int s);
+int init_mfma_ktab_row(int q);
+hipError_t launch_init_tables(const Geom &g, const Tables &tb, const Sources &src, void *ktab, hipStream_t st);
+hipError_t launch_init_etab(const Geom &g, const PhaseDev &ph, const Sources &src, void *etab, hipStream_t st);
+hipError_t launch_init_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, const Sources &src,
+                            const void *ktab, const void *etab, const void *f, void *fsorted, void *w, int nrhs,
+                            size_t plane, hipStream_t st);
+hipError_t launch_init_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, const Sources &src,
+                                const void *ktab, const void *etab, const void *w, void *f, int nrhs,
+                                size_t plane, hipStream_t st);
+
 // Adjoint launchers: exact conjugate transposes of the above.
 hipError_t launch_term_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,
                            const void *u, void *w_out, hipStream_t st);

@@ -1,7 +1,7 @@
 // Host side of the C ABI: argument validation, the plan (trees of Sec. 4
 // step 1, interpolation tables, workspace), and the level schedule that
 // drives the kernels of fio_kernels_fwd.hip, fio_kernels_adj.hip,
-// fio_kernels_mfma.hip and fio_kernels_tan.hip.
+// fio_kernels_init.hip, fio_kernels_mfma.hip and fio_kernels_tan.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -92,6 +92,9 @@ struct fio_plan_s {
     size_t total_bytes = 0;  // all device memory of the plan
     void *w0 = nullptr, *w1 = nullptr;
     void *t0 = nullptr, *t1 = nullptr;  // tangent workspace (3 planes each), when nrhs_max < 3
+    bool init_mm = false;               // initialisation on the matrix cores
+    void *ktab = nullptr, *etab = nullptr;
+    bool etab_ok = false;               // etab holds the kernel values of the current phase
     void *dtab = nullptr;    // tables
     int32_t *d_idx = nullptr, *d_off = nullptr;
     double2 *d_p = nullptr;
@@ -113,6 +116,8 @@ void free_plan(fio_plan_s *p) {
     (void)hipFree(p->w1);
     (void)hipFree(p->t0);
     (void)hipFree(p->t1);
+    (void)hipFree(p->ktab);
+    (void)hipFree(p->etab);
     (void)hipFree(p->dtab);
     (void)hipFree(p->d_idx);
     (void)hipFree(p->d_off);
@@ -332,6 +337,23 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     p->geom.s = s;
     p->geom.lm = lm;
     p->geom.rho_scale = std::sqrt(2.0) / 2.0 * N;
+
+    // tables of the initialisation on the matrix cores
+    p->init_mm = dtype == FIO_C64 && init_mfma_supported(q, s);
+    if (p->init_mm) {
+        const size_t kbytes = n2 * (size_t)init_mfma_ktab_row(q) * 4, ebytes = n2 * 64 * 8;
+        if ((rc = dmalloc(&p->ktab, kbytes, &p->total_bytes, "init K table")) ||
+            (rc = dmalloc(&p->etab, ebytes, &p->total_bytes, "init kernel-value table"))) {
+            free_plan(p);
+            return rc;
+        }
+        Sources srcs{p->d_idx, p->d_p, p->d_off};
+        if ((e = launch_init_tables(p->geom, p->tb, srcs, p->ktab, nullptr)) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess) {
+            free_plan(p);
+            return hip_fail(e, "init K table");
+        }
+    }
     *out = p;
     return FIO_OK;
 }
@@ -340,6 +362,9 @@ int fio_set_phase(fio_plan_t plan, const fio_phase_t *phase) {
     int rc = check_plan(plan);
     if (rc) return rc;
     if ((rc = validate_phase(phase))) return rc;
+    if (phase->kind != plan->phase.kind || phase->a1 != plan->phase.a1 || phase->a2 != plan->phase.a2 ||
+        phase->eta1 != plan->phase.eta1 || phase->eta2 != plan->phase.eta2)
+        plan->etab_ok = false;
     plan->phase = *phase;
     return FIO_OK;
 }
@@ -363,6 +388,16 @@ int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info) {
     return FIO_OK;
 }
 
+// The kernel-value table of the matrix-core initialisation, remade after a
+// phase change (on the stream of the call that needs it).
+static hipError_t ensure_etab(fio_plan_t p, const PhaseDev &ph, const Sources &src, hipStream_t st) {
+    if (p->etab_ok) return hipSuccess;
+    Timed tm(p, FIO_K_TABLES, st);
+    hipError_t e = launch_init_etab(p->geom, ph, src, p->etab, st);
+    if (e == hipSuccess) p->etab_ok = true;
+    return e;
+}
+
 // Forward pipeline for `nr` <= nrhs_max right-hand sides (f, u: nr planes of
 // N^2); stops after `last_stage` (-1: run to the potentials) and returns the
 // buffer holding that stage's weights through *wlast.
@@ -375,9 +410,18 @@ static int run_forward(fio_plan_t p, const void *f, void *u, int nr, int last_st
     char *a = (char *)p->w0, *b = (char *)p->w1;
     int stage = 0;
     hipError_t e = hipSuccess;
-    for (int r = 0; r < nr && e == hipSuccess; ++r) {
-        Timed tm(p, FIO_K_INIT, st);
-        e = launch_init(p->dtype, p->geom, ph, p->tb, src, (const char *)f + r * fstep, a + r * p->wbytes, st);
+    if (p->init_mm) {
+        e = ensure_etab(p, ph, src, st);
+        if (e == hipSuccess) {
+            Timed tm(p, FIO_K_INIT, st);
+            e = launch_init_mfma(p->geom, ph, p->tb, src, p->ktab, p->etab, f, b, a, nr, p->plane, st);
+        }
+    } else {
+        for (int r = 0; r < nr && e == hipSuccess; ++r) {
+            Timed tm(p, FIO_K_INIT, st);
+            e = launch_init(p->dtype, p->geom, ph, p->tb, src, (const char *)f + r * fstep, a + r * p->wbytes,
+                            st);
+        }
     }
     if (e != hipSuccess) return hip_fail(e, "init launch");
     if (last_stage == stage) {
@@ -464,9 +508,18 @@ static int run_adjoint(fio_plan_t p, const void *u, void *f, int nr, hipStream_t
         if (e != hipSuccess) return hip_fail(e, "p-level^H launch");
         std::swap(a, b);
     }
-    for (int r = 0; r < nr && e == hipSuccess; ++r) {
-        Timed tm(p, FIO_K_INIT_ADJ, st);
-        e = launch_init_adj(p->dtype, p->geom, ph, p->tb, src, a + r * p->wbytes, (char *)f + r * fstep, st);
+    if (p->init_mm) {
+        e = ensure_etab(p, ph, src, st);
+        if (e == hipSuccess) {
+            Timed tm(p, FIO_K_INIT_ADJ, st);
+            e = launch_init_adj_mfma(p->geom, ph, p->tb, src, p->ktab, p->etab, a, f, nr, p->plane, st);
+        }
+    } else {
+        for (int r = 0; r < nr && e == hipSuccess; ++r) {
+            Timed tm(p, FIO_K_INIT_ADJ, st);
+            e = launch_init_adj(p->dtype, p->geom, ph, p->tb, src, a + r * p->wbytes, (char *)f + r * fstep,
+                                st);
+        }
     }
     if (e != hipSuccess) return hip_fail(e, "initialisation^H launch");
     return FIO_OK;
