@@ -182,14 +182,26 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
             E2[kk] = cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]));
         }
     }
+    // inputs of the thread's row, loaded one right-hand side ahead
+    cpx<T> nx[Q];
+    auto load_row = [&](int r) {
+        const cpx<T> *src = win + r * plane + ((size_t)(4 * mAp + 2 * j1 + j2) * nBl + mB) * QQ + t1 * Q;
+#pragma unroll
+        for (int t2 = 0; t2 < Q; ++t2) nx[t2] = src[t2];
+    };
+    constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
+    if (PF && active) load_row(0);
     for (int r = 0; r < (HOIST ? nrhs : 1); ++r) {
         {
             cpx<T> acc0[Q], acc1[Q];   // c1 = 0, 1
 #pragma unroll
             for (int t = 0; t < Q; ++t) acc0[t] = acc1[t] = {(T)0, (T)0};
             if (active) {
-                const cpx<T> *src =
-                    win + r * plane + ((size_t)(4 * mAp + 2 * j1 + j2) * nBl + mB) * QQ + t1 * Q;
+                if (!PF) load_row(r);
+                cpx<T> in[Q];
+#pragma unroll
+                for (int k = 0; k < Q; ++k) in[k] = nx[k];
+                if (PF && r + 1 < nrhs) load_row(r + 1);
                 const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
                 const double xa1 = box_node(a1, level, tb.z[t1]);
 #pragma unroll
@@ -205,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
                         e0 = cis<T>(r0c[bbl][0] * G);
                         e1 = cis<T>(r0c[bbl][1] * G);
                     }
-                    const cpx<T> d = src[t2];
+                    const cpx<T> d = in[t2];
                     const cpx<T> v0 = cmulc(d, e0);
                     const cpx<T> v1 = cmulc(d, e1);
 #pragma unroll
@@ -219,10 +231,10 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
             // add the partner lane's (other j2) partial rows
 #pragma unroll
             for (int t = 0; t < Q; ++t) {
-                acc0[t].re += __shfl_xor(acc0[t].re, 1);
-                acc0[t].im += __shfl_xor(acc0[t].im, 1);
-                acc1[t].re += __shfl_xor(acc1[t].re, 1);
-                acc1[t].im += __shfl_xor(acc1[t].im, 1);
+                acc0[t].re += swap_adjacent_lanes(acc0[t].re);
+                acc0[t].im += swap_adjacent_lanes(acc0[t].im);
+                acc1[t].re += swap_adjacent_lanes(acc1[t].re);
+                acc1[t].im += swap_adjacent_lanes(acc1[t].im);
             }
             if (active && j2 == 0) {
 #pragma unroll
@@ -497,15 +509,27 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
             for (int kk = 0; kk < H1; ++kk) E2[jj][kk] = cis<T>(rc[bbl][c1 * Q + min(h * H1 + kk, Q - 1)] * G);
         }
     }
+    // inputs of the thread's row, loaded one right-hand side ahead
+    cpx<T> nx[Q];
+    auto load_row = [&](int ri) {
+        const cpx<T> *src = win + ri * plane + ((size_t)(4 * mAp + j) * nBl + mB) * QQ + t1 * Q;
+#pragma unroll
+        for (int t2 = 0; t2 < Q; ++t2) nx[t2] = src[t2];
+    };
+    constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
+    if (PF && active) load_row(0);
     for (int ri = 0; ri < (HOIST ? nrhs : 1); ++ri) {
         if (active) {
-            const cpx<T> *src = win + ri * plane + ((size_t)(4 * mAp + j) * nBl + mB) * QQ + t1 * Q;
+            if (!PF) load_row(ri);
+            cpx<T> in[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) in[k] = nx[k];
             cpx<T> acc[Q];
 #pragma unroll
             for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
 #pragma unroll
             for (int t2 = 0; t2 < Q; ++t2) {
-                const cpx<T> gv = cmul(src[t2], HOIST ? E1[t2] : cis<T>(rhoB * Gb[bbl][j][t2]));
+                const cpx<T> gv = cmul(in[t2], HOIST ? E1[t2] : cis<T>(rhoB * Gb[bbl][j][t2]));
 #pragma unroll
                 for (int p2 = 0; p2 < Q; ++p2) crfma(acc[p2], Ms[c2a][t2][p2], gv);
             }
@@ -513,6 +537,9 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
             for (int p2 = 0; p2 < Q; ++p2) Y[bbl][j][c2a][t1 * Q + p2] = acc[p2];
         }
         __syncthreads();
+        // the next right-hand side's row is loaded during the (longer) second
+        // pass (a barrier waits for every outstanding load)
+        if (PF && active && ri + 1 < nrhs) load_row(ri + 1);
         if (active) {
             cpx<T> acc[H1];
 #pragma unroll

@@ -78,6 +78,18 @@ template <typename T>
 constexpr int swadj_rc() { return sizeof(T) == 4 ? 4 : 2; }
 
 
+// The value of the neighbouring lane (lane ^ 1), through a DPP quad
+// permutation [1,0,3,2] on the vector ALU (no LDS-pipe shuffle).
+__device__ __forceinline__ float swap_adjacent_lanes(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double swap_adjacent_lanes(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 #define FIO_DISPATCH_Q(q, MACRO) \
     switch (q) {                 \
         case 3: MACRO(3); break; \

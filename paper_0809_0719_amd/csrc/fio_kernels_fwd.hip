@@ -202,19 +202,35 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
             for (int k = 0; k < H1; ++k) Eb[k] = cis<T>(rb[bbl][min(h * H1 + k, Q - 1)] * GB);
         }
     }
+    // inputs of the thread's row, loaded one right-hand side ahead
+    cpx<T> nx[2 * Q];
+    auto load_row = [&](int r) {
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const cpx<T> *src = win + r * plane + (blk * 4 + 2 * c1 + c2) * QQ + tp1 * Q;
+#pragma unroll
+            for (int tp2 = 0; tp2 < Q; ++tp2) nx[c2 * Q + tp2] = src[tp2];
+        }
+    };
+    constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
+    if (PF && active) load_row(0);
     for (int r = 0; r < (HOIST ? nrhs : 1); ++r) {
         if (active) {
+            if (!PF) load_row(r);
+            cpx<T> in[2 * Q];
+#pragma unroll
+            for (int k = 0; k < 2 * Q; ++k) in[k] = nx[k];
+            if (PF && r + 1 < nrhs) load_row(r + 1);
             // first pass: row (c1, t'1)
             cpx<T> acc[Q];
 #pragma unroll
             for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
 #pragma unroll
             for (int c2 = 0; c2 < 2; ++c2) {
-                const cpx<T> *src = win + r * plane + (blk * 4 + 2 * c1 + c2) * QQ + tp1 * Q;
 #pragma unroll
                 for (int tp2 = 0; tp2 < Q; ++tp2) {
                     const cpx<T> e = HOIST ? Ea[c2 * Q + tp2] : cis<T>(rhoA * Gc[bbl][j][c2 * Q + tp2]);
-                    const cpx<T> v = cmul(e, src[tp2]);
+                    const cpx<T> v = cmul(e, in[c2 * Q + tp2]);
 #pragma unroll
                     for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Mt[c2][tp2][tt], v);
                 }
@@ -350,10 +366,13 @@ __global__ __launch_bounds__(NT) void k_switch(Geom g, PhaseDev ph, Tables tb, c
 //   delta^{AB}_t = sum_c E(x^A_t, p0(B_c)) sum_t' M_a1[t'1][t1] M_a2[t'2][t2]
 //                    conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t'
 // for the four children A = (a1, a2) of A_p.  The prefactor depends only on
-// (A_p, B_c) and is applied once per block; the first (second-dimension)
-// pass depends on A only through a2, so it is shared by the children with
-// the same a2.  Threads: prefactor (c, t'1) rows; first pass (a2, c, t'1)
-// rows; second pass (A, t2, half) columns with the remodulation per B_c.
+// (A_p, B_c); the first (second-dimension) pass depends on A only through
+// a2, so it is shared by the children with the same a2.  Threads: first pass
+// (a2, c, t'1) rows; second pass (A, t2, half) columns with the remodulation
+// per B_c.  One right-hand side: the prefactor is applied once per row
+// (c, t'1) in a phase of its own.  Several: every first-pass thread applies
+// its row's prefactor itself (kernel values hoisted for all right-hand
+// sides), which saves a barrier per right-hand side.
 // ===========================================================================
 template <typename T, int Q, bool HOIST>
 __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, int level,
@@ -427,15 +446,15 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
         return cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]));
     };
     if (HOIST && active) {
-        if (rr < 4 * Q) {
-            const int c2 = pc & 1, c1 = pc >> 1;
-            const double xa1 = box_node(ap1, level - 1, tb.z[ptp1]);
+        // batched: every first-pass thread (a2, c, t'1) applies the prefactor
+        // of its own row (c, t'1) itself
+        const int c2 = ac & 1, c1 = ac >> 1;
+        const double xa1 = box_node(ap1, level - 1, tb.z[atp1]);
 #pragma unroll
-            for (int tp2 = 0; tp2 < Q; ++tp2) {
-                const XP xp = make_xp_sc(ph, xa1, box_node(ap2, level - 1, tb.z[tp2]), sp[bbl][0][ptp1],
-                                         cp[bbl][0][ptp1], sp[bbl][1][tp2], cp[bbl][1][tp2]);
-                Ep[tp2] = cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]));
-            }
+        for (int tp2 = 0; tp2 < Q; ++tp2) {
+            const XP xp = make_xp_sc(ph, xa1, box_node(ap2, level - 1, tb.z[tp2]), sp[bbl][0][atp1],
+                                     cp[bbl][0][atp1], sp[bbl][1][tp2], cp[bbl][1][tp2]);
+            Ep[tp2] = cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]));
         }
         const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
         const double xb2 = box_node(a2, level, tb.z[t2]);
@@ -452,90 +471,123 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
             E2[3][kk] = cis<T>(r0c[bbl][1] * G1);
         }
     }
-    for (int r = 0; r < (HOIST ? nrhs : 1); ++r) {
-        // prefactor conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t': row (c, t'1)
-        if (active && rr < 4 * Q) {
-            const cpx<T> *src = win + r * plane + (blk * 4 + pc) * QQ + ptp1 * Q;
+    if constexpr (HOIST) {
+        // inputs of the first-pass row, loaded one right-hand side ahead (during
+        // the second pass: a barrier waits for every outstanding load)
+        cpx<T> nx[Q];
+        auto load_row = [&](int r) {
+            const cpx<T> *src = win + r * plane + (blk * 4 + ac) * QQ + atp1 * Q;
 #pragma unroll
-            for (int tp2 = 0; tp2 < Q; ++tp2)
-                v[bbl][pc][ptp1 * Q + tp2] = cmulc(src[tp2], HOIST ? Ep[tp2] : pre_exp(tp2));
-        }
-        __syncthreads();
-        // first pass (second dimension): Y[a2][c][t'1][t2] = sum_t'2 M_a2[t'2][t2] v[c][t'1][t'2]
-        if (active) {
-            cpx<T> acc[Q];
-#pragma unroll
-            for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
-#pragma unroll
-            for (int tp2 = 0; tp2 < Q; ++tp2) {
-                const cpx<T> vv = v[bbl][ac][atp1 * Q + tp2];
-#pragma unroll
-                for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Ms[a2c][tp2][tt], vv);
-            }
-#pragma unroll
-            for (int tt = 0; tt < Q; ++tt) Y[bbl][a2c][ac][atp1 * Q + tt] = acc[tt];
-        }
-        __syncthreads();
-        // second pass (first dimension), remodulation E(x^A_t, p0(B_c)), sum over c
-        cpx<T> out[H1];
-        if constexpr (!HOIST) {
+            for (int tp2 = 0; tp2 < Q; ++tp2) nx[tp2] = src[tp2];
+        };
+        if (active) load_row(0);
+        for (int r = 0; r < nrhs; ++r) {
+            // first pass with the prefactor: Y[a2][c][t'1][t2] =
+            //   sum_t'2 M_a2[t'2][t2] conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t'
             if (active) {
-                const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
-                double G0[H1], G1[H1];
-                const double xb2 = box_node(a2, level, tb.z[t2]);
+                cpx<T> acc[Q];
 #pragma unroll
-                for (int kk = 0; kk < H1; ++kk) {
-                    const int t1 = min(h * H1 + kk, Q - 1);
-                    const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), xb2, sj[bbl][0][j1][t1],
-                                             cj[bbl][0][j1][t1], sj[bbl][1][j2][t2], cj[bbl][1][j2][t2]);
-                    G0[kk] = phase_dir(xp, ct0[bbl][0], st0[bbl][0]);
-                    G1[kk] = phase_dir(xp, ct0[bbl][1], st0[bbl][1]);
-                    out[kk] = {(T)0, (T)0};
+                for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
+#pragma unroll
+                for (int tp2 = 0; tp2 < Q; ++tp2) {
+                    const cpx<T> vv = cmulc(nx[tp2], Ep[tp2]);
+#pragma unroll
+                    for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Ms[a2c][tp2][tt], vv);
                 }
-#pragma unroll 1
+#pragma unroll
+                for (int tt = 0; tt < Q; ++tt) Y[bbl][a2c][ac][atp1 * Q + tt] = acc[tt];
+            }
+            __syncthreads();
+            if (active && r + 1 < nrhs) load_row(r + 1);
+            if (active) {
+                cpx<T> out[H1];
+#pragma unroll
+                for (int kk = 0; kk < H1; ++kk) out[kk] = {(T)0, (T)0};
+#pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const int c1 = c >> 1, c2 = c & 1;
                     cpx<T> col[Q];
 #pragma unroll
                     for (int tp1 = 0; tp1 < Q; ++tp1) col[tp1] = Y[bbl][j2][c][tp1 * Q + t2];
-                    const double rho = r0c[bbl][c1];
 #pragma unroll
                     for (int kk = 0; kk < H1; ++kk) {
                         const int t1 = min(h * H1 + kk, Q - 1);
                         cpx<T> z = {(T)0, (T)0};
 #pragma unroll
                         for (int tp1 = 0; tp1 < Q; ++tp1) crfma(z, Ms[j1][tp1][t1], col[tp1]);
-                        cfma(out[kk], cis<T>(rho * (c2 ? G1[kk] : G0[kk])), z);
+                        cfma(out[kk], E2[c][kk], z);
                     }
                 }
-            }
-        } else if (active) {
-#pragma unroll
-            for (int kk = 0; kk < H1; ++kk) out[kk] = {(T)0, (T)0};
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                cpx<T> col[Q];
-#pragma unroll
-                for (int tp1 = 0; tp1 < Q; ++tp1) col[tp1] = Y[bbl][j2][c][tp1 * Q + t2];
+                cpx<T> *dst = wout + r * plane + ((size_t)(4 * mAp + jj) * nBl + mB) * QQ;
 #pragma unroll
                 for (int kk = 0; kk < H1; ++kk) {
-                    const int t1 = min(h * H1 + kk, Q - 1);
-                    cpx<T> z = {(T)0, (T)0};
-#pragma unroll
-                    for (int tp1 = 0; tp1 < Q; ++tp1) crfma(z, Ms[j1][tp1][t1], col[tp1]);
-                    cfma(out[kk], E2[c][kk], z);
+                    const int t1 = h * H1 + kk;
+                    if (t1 < Q) dst[t1 * Q + t2] = out[kk];
                 }
             }
+            __syncthreads();
         }
-        if (active) {
-            cpx<T> *dst = wout + r * plane + ((size_t)(4 * mAp + jj) * nBl + mB) * QQ;
+        return;
+    }
+    // one right-hand side: prefactor conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t'
+    // once per row (c, t'1)
+    if (active && rr < 4 * Q) {
+        const cpx<T> *src = win + (blk * 4 + pc) * QQ + ptp1 * Q;
+#pragma unroll
+        for (int tp2 = 0; tp2 < Q; ++tp2) v[bbl][pc][ptp1 * Q + tp2] = cmulc(src[tp2], pre_exp(tp2));
+    }
+    __syncthreads();
+    // first pass (second dimension): Y[a2][c][t'1][t2] = sum_t'2 M_a2[t'2][t2] v[c][t'1][t'2]
+    if (active) {
+        cpx<T> acc[Q];
+#pragma unroll
+        for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
+#pragma unroll
+        for (int tp2 = 0; tp2 < Q; ++tp2) {
+            const cpx<T> vv = v[bbl][ac][atp1 * Q + tp2];
+#pragma unroll
+            for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Ms[a2c][tp2][tt], vv);
+        }
+#pragma unroll
+        for (int tt = 0; tt < Q; ++tt) Y[bbl][a2c][ac][atp1 * Q + tt] = acc[tt];
+    }
+    __syncthreads();
+    // second pass (first dimension), remodulation E(x^A_t, p0(B_c)), sum over c
+    if (active) {
+        cpx<T> out[H1];
+        const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
+        double G0[H1], G1[H1];
+        const double xb2 = box_node(a2, level, tb.z[t2]);
+#pragma unroll
+        for (int kk = 0; kk < H1; ++kk) {
+            const int t1 = min(h * H1 + kk, Q - 1);
+            const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), xb2, sj[bbl][0][j1][t1],
+                                     cj[bbl][0][j1][t1], sj[bbl][1][j2][t2], cj[bbl][1][j2][t2]);
+            G0[kk] = phase_dir(xp, ct0[bbl][0], st0[bbl][0]);
+            G1[kk] = phase_dir(xp, ct0[bbl][1], st0[bbl][1]);
+            out[kk] = {(T)0, (T)0};
+        }
+#pragma unroll 1
+        for (int c = 0; c < 4; ++c) {
+            const int c1 = c >> 1, c2 = c & 1;
+            cpx<T> col[Q];
+#pragma unroll
+            for (int tp1 = 0; tp1 < Q; ++tp1) col[tp1] = Y[bbl][j2][c][tp1 * Q + t2];
+            const double rho = r0c[bbl][c1];
 #pragma unroll
             for (int kk = 0; kk < H1; ++kk) {
-                const int t1 = h * H1 + kk;
-                if (t1 < Q) dst[t1 * Q + t2] = out[kk];
+                const int t1 = min(h * H1 + kk, Q - 1);
+                cpx<T> z = {(T)0, (T)0};
+#pragma unroll
+                for (int tp1 = 0; tp1 < Q; ++tp1) crfma(z, Ms[j1][tp1][t1], col[tp1]);
+                cfma(out[kk], cis<T>(rho * (c2 ? G1[kk] : G0[kk])), z);
             }
         }
-        __syncthreads();
+        cpx<T> *dst = wout + ((size_t)(4 * mAp + jj) * nBl + mB) * QQ;
+#pragma unroll
+        for (int kk = 0; kk < H1; ++kk) {
+            const int t1 = h * H1 + kk;
+            if (t1 < Q) dst[t1 * Q + t2] = out[kk];
+        }
     }
 }
 
