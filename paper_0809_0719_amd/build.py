@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfio.so")
 
-SOURCES = ["fio_plan.cpp", "fio_kernels_fwd.hip", "fio_kernels_adj.hip", "fio_kernels_init.hip", "fio_kernels_mfma.hip",
+SOURCES = ["fio_plan.cpp", "fio_kernels_fwd.hip", "fio_kernels_adj.hip", "fio_kernels_init.hip", "fio_kernels_term.hip",
+           "fio_kernels_mfma.hip",
            "fio_kernels_tan.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,6 +1,7 @@
 // Internal definitions shared by the host plan (fio_plan.cpp) and the HIP
-// kernels (fio_kernels_fwd.hip, fio_kernels_adj.hip, fio_kernels_mfma.hip,
-// fio_kernels_tan.hip).  Not part of the public ABI.
+// kernels (fio_kernels_fwd.hip, fio_kernels_adj.hip, fio_kernels_init.hip,
+// fio_kernels_term.hip, fio_kernels_mfma.hip, fio_kernels_tan.hip).  Not part
+// of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -90,6 +91,13 @@ hipError_t launch_init_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb,
 hipError_t launch_init_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, const Sources &src,
                                 const void *ktab, const void *etab, const void *w, void *f, int nrhs,
                                 size_t plane, hipStream_t st);
+
+// Termination and its adjoint for `nrhs` > 1 right-hand sides in one launch
+// (fio_kernels_term.hip): weights planes `plane` apart, potentials `uplane`.
+hipError_t launch_term_batch(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, const void *w_in,
+                             void *u, int nrhs, size_t plane, size_t uplane, hipStream_t st);
+hipError_t launch_term_adj_batch(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, const void *u,
+                                 void *w_out, int nrhs, size_t plane, size_t uplane, hipStream_t st);
 
 // Adjoint launchers: exact conjugate transposes of the above.
 hipError_t launch_term_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,

@@ -1,7 +1,8 @@
 // Host side of the C ABI: argument validation, the plan (trees of Sec. 4
 // step 1, interpolation tables, workspace), and the level schedule that
 // drives the kernels of fio_kernels_fwd.hip, fio_kernels_adj.hip,
-// fio_kernels_init.hip, fio_kernels_mfma.hip and fio_kernels_tan.hip.
+// fio_kernels_init.hip, fio_kernels_term.hip, fio_kernels_mfma.hip and
+// fio_kernels_tan.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -467,9 +468,12 @@ static int run_forward(fio_plan_t p, const void *f, void *u, int nr, int last_st
         }
     }
     if (last_stage >= 0) return fail(FIO_EINVAL, "stage %d out of range (last is %d)", last_stage, stage);
-    for (int r = 0; r < nr && e == hipSuccess; ++r) {
+    if (nr > 1) {
         Timed tm(p, FIO_K_TERM, st);
-        e = launch_term(p->dtype, p->geom, ph, p->tb, a + r * p->wbytes, (char *)u + r * fstep, st);
+        e = launch_term_batch(p->dtype, p->geom, ph, p->tb, a, u, nr, p->plane, (size_t)p->N * p->N, st);
+    } else {
+        Timed tm(p, FIO_K_TERM, st);
+        e = launch_term(p->dtype, p->geom, ph, p->tb, a, u, st);
     }
     if (e != hipSuccess) return hip_fail(e, "termination launch");
     return FIO_OK;
@@ -482,9 +486,12 @@ static int run_adjoint(fio_plan_t p, const void *u, void *f, int nr, hipStream_t
     const size_t fstep = (size_t)p->N * p->N * csize;
     char *a = (char *)p->w0, *b = (char *)p->w1;
     hipError_t e = hipSuccess;
-    for (int r = 0; r < nr && e == hipSuccess; ++r) {
+    if (nr > 1) {
         Timed tm(p, FIO_K_TERM_ADJ, st);
-        e = launch_term_adj(p->dtype, p->geom, ph, p->tb, (const char *)u + r * fstep, a + r * p->wbytes, st);
+        e = launch_term_adj_batch(p->dtype, p->geom, ph, p->tb, u, a, nr, p->plane, (size_t)p->N * p->N, st);
+    } else {
+        Timed tm(p, FIO_K_TERM_ADJ, st);
+        e = launch_term_adj(p->dtype, p->geom, ph, p->tb, u, a, st);
     }
     if (e != hipSuccess) return hip_fail(e, "termination^H launch");
     for (int l = p->L - p->s; l >= p->lm + 1; --l) {

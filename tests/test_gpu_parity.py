@@ -262,3 +262,23 @@ def test_batched_equals_one_by_one(case, dtype):
     if case[0] <= 64:
         _, u_ref, _ = oracle_forward(N, q, ph, s, lm, 36)
         assert rel_l2(U[6].cpu().numpy(), u_ref) <= (FP64_TOL if dtype == torch.complex128 else FP32_TOL)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_batched_termination_more_than_64_rhs(dtype):
+    """The batched termination and its adjoint hold 16 right-hand sides per
+    wave and pass (64 per workgroup); 70 right-hand sides take a second,
+    ragged pass.  Against one-at-a-time applies (N = 64, s = 3: every grid
+    point of a box A is a lane)."""
+    import paper_0809_0719_amd as fio
+    N, q = 64, 5
+    one = fio.Plan(N, q, fio.Phase(), dtype=dtype)
+    many = fio.Plan(N, q, fio.Phase(), dtype=dtype, nrhs_max=70)
+    F = _dev(white_noise(N, 50, nrhs=70), dtype)
+    U = many.apply(F)
+    G = many.adjoint(U)
+    tol = 1e-13 if dtype == torch.complex128 else 2e-6
+    for r in (0, 1, 63, 64, 69):
+        e1 = rel_l2(U[r].cpu().numpy(), one.apply(F[r]).cpu().numpy())
+        e2 = rel_l2(G[r].cpu().numpy(), one.adjoint(U[r]).cpu().numpy())
+        assert e1 <= tol and e2 <= tol, (r, e1, e2)
