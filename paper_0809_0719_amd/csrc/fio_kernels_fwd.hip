@@ -231,8 +231,10 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
                 for (int tp2 = 0; tp2 < Q; ++tp2) {
                     const cpx<T> e = HOIST ? Ea[c2 * Q + tp2] : cis<T>(rhoA * Gc[bbl][j][c2 * Q + tp2]);
                     const cpx<T> v = cmul(e, in[c2 * Q + tp2]);
+                    // M_c2[tt][t'2]: the same for every thread, read through the
+                    // scalar cache (SGPR operands) rather than as LDS broadcasts
 #pragma unroll
-                    for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Mt[c2][tp2][tt], v);
+                    for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Mg[(c2 * Q + tt) * Q + tp2], v);
                 }
             }
 #pragma unroll
