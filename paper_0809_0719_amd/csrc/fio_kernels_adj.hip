@@ -490,18 +490,30 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
         if (rr < Q) Gb[bbl][j][rr] = phase_dir(xp, ctb[bbl][rr], stb[bbl][rr]);
     }
     __syncthreads();
-    // first pass: thread (j, c2, t1); second pass: thread (c, t'2, half), r = c * 2q + h * q + t'2
-    const int c2a = rr / Q, t1 = rr - c2a * Q;
+    // first pass: the child index c2 is the same for a pair of waves (threads
+    // [128 c2, 128 c2 + 128)), row (block, j, t1) within it, so the factors
+    // M_c2[t2][t'2] are wave-uniform (scalar operands); second pass: thread
+    // (c, t'2, half) of its block, r = c * 2q + h * q + t'2
+    const int fc2 = __builtin_amdgcn_readfirstlane(tid / (NT / 2)), fi = tid - fc2 * (NT / 2);
+    const int fb = fi / (4 * Q), fk = fi - fb * (4 * Q), fj = fk / Q, t1 = fk - fj * Q;
+    const size_t fblk = (size_t)blockIdx.x * BPW + fb;
+    const bool factive = fb < BPW && fblk < nblk;
+    uint32_t fmB = 0, fmAp = 0;
+    if (factive) {
+        fmB = (uint32_t)(fblk & (nBl - 1));
+        fmAp = (uint32_t)(fblk >> (2 * lB));
+    }
     const int c = r / (2 * Q), k = r - c * 2 * Q;
     const int h = k / Q, tp2 = k - h * Q;
     const int c1 = c >> 1, c2 = c & 1;
     // exponentials shared by all right-hand sides
     cpx<T> E1[Q], E2[4][H1];
-    const double rhoB = rb[bbl][t1];
-    if (HOIST && active) {
-        const double rho = rhoB;
+    const double rhoB = factive ? rb[fb][t1] : 0.0;
+    if (HOIST && factive) {
 #pragma unroll
-        for (int t2 = 0; t2 < Q; ++t2) E1[t2] = cis<T>(rho * Gb[bbl][j][t2]);
+        for (int t2 = 0; t2 < Q; ++t2) E1[t2] = cis<T>(rhoB * Gb[fb][fj][t2]);
+    }
+    if (HOIST && active) {
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const double G = Gc[bbl][jj][c2 * Q + tp2];
@@ -512,14 +524,14 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
     // inputs of the thread's row, loaded one right-hand side ahead
     cpx<T> nx[Q];
     auto load_row = [&](int ri) {
-        const cpx<T> *src = win + ri * plane + ((size_t)(4 * mAp + j) * nBl + mB) * QQ + t1 * Q;
+        const cpx<T> *src = win + ri * plane + ((size_t)(4 * fmAp + fj) * nBl + fmB) * QQ + t1 * Q;
 #pragma unroll
         for (int t2 = 0; t2 < Q; ++t2) nx[t2] = src[t2];
     };
     constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
-    if (PF && active) load_row(0);
+    if (PF && factive) load_row(0);
     for (int ri = 0; ri < (HOIST ? nrhs : 1); ++ri) {
-        if (active) {
+        if (factive) {
             if (!PF) load_row(ri);
             cpx<T> in[Q];
 #pragma unroll
@@ -529,17 +541,17 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
             for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
 #pragma unroll
             for (int t2 = 0; t2 < Q; ++t2) {
-                const cpx<T> gv = cmul(in[t2], HOIST ? E1[t2] : cis<T>(rhoB * Gb[bbl][j][t2]));
+                const cpx<T> gv = cmul(in[t2], HOIST ? E1[t2] : cis<T>(rhoB * Gb[fb][fj][t2]));
 #pragma unroll
-                for (int p2 = 0; p2 < Q; ++p2) crfma(acc[p2], Ms[c2a][t2][p2], gv);
+                for (int p2 = 0; p2 < Q; ++p2) crfma(acc[p2], Mg[(fc2 * Q + t2) * Q + p2], gv);
             }
 #pragma unroll
-            for (int p2 = 0; p2 < Q; ++p2) Y[bbl][j][c2a][t1 * Q + p2] = acc[p2];
+            for (int p2 = 0; p2 < Q; ++p2) Y[fb][fj][fc2][t1 * Q + p2] = acc[p2];
         }
         __syncthreads();
         // the next right-hand side's row is loaded during the (longer) second
         // pass (a barrier waits for every outstanding load)
-        if (PF && active && ri + 1 < nrhs) load_row(ri + 1);
+        if (PF && factive && ri + 1 < nrhs) load_row(ri + 1);
         if (active) {
             cpx<T> acc[H1];
 #pragma unroll

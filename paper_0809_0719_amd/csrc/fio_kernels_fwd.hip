@@ -447,17 +447,28 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
                                  sp[bbl][0][ptp1], cp[bbl][0][ptp1], sp[bbl][1][tp2], cp[bbl][1][tp2]);
         return cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]));
     };
-    if (HOIST && active) {
-        // batched: every first-pass thread (a2, c, t'1) applies the prefactor
-        // of its own row (c, t'1) itself
-        const int c2 = ac & 1, c1 = ac >> 1;
-        const double xa1 = box_node(ap1, level - 1, tb.z[atp1]);
+    // batched first pass: the child's a2 is the same for a pair of waves
+    // (threads [128 a2, 128 a2 + 128)), row (block, c, t'1) within it, so the
+    // factors M_a2[t'2][t2] are wave-uniform (scalar operands)
+    // (fa2 is uniform over the wave: make that explicit for the compiler)
+    const int fa2 = __builtin_amdgcn_readfirstlane(tid / (NT / 2)), fi = tid - fa2 * (NT / 2);
+    const int fb = fi / (4 * Q), fk = fi - fb * (4 * Q), fac = fk / Q, fatp1 = fk - fac * Q;
+    const size_t fblk = (size_t)blockIdx.x * BPW + fb;
+    const bool factive = fb < BPW && fblk < nblk;
+    int fap1 = 0, fap2 = 0;
+    if (factive) morton_decode((uint32_t)(fblk >> (2 * lB)), fap1, fap2);
+    if (HOIST && factive) {
+        // every first-pass thread applies the prefactor of its own row (c, t'1)
+        const int c2 = fac & 1, c1 = fac >> 1;
+        const double xa1 = box_node(fap1, level - 1, tb.z[fatp1]);
 #pragma unroll
         for (int tp2 = 0; tp2 < Q; ++tp2) {
-            const XP xp = make_xp_sc(ph, xa1, box_node(ap2, level - 1, tb.z[tp2]), sp[bbl][0][atp1],
-                                     cp[bbl][0][atp1], sp[bbl][1][tp2], cp[bbl][1][tp2]);
-            Ep[tp2] = cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]));
+            const XP xp = make_xp_sc(ph, xa1, box_node(fap2, level - 1, tb.z[tp2]), sp[fb][0][fatp1],
+                                     cp[fb][0][fatp1], sp[fb][1][tp2], cp[fb][1][tp2]);
+            Ep[tp2] = cis<T>(r0c[fb][c1] * phase_dir(xp, ct0[fb][c2], st0[fb][c2]));
         }
+    }
+    if (HOIST && active) {
         const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
         const double xb2 = box_node(a2, level, tb.z[t2]);
 #pragma unroll
@@ -478,15 +489,15 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
         // the second pass: a barrier waits for every outstanding load)
         cpx<T> nx[Q];
         auto load_row = [&](int r) {
-            const cpx<T> *src = win + r * plane + (blk * 4 + ac) * QQ + atp1 * Q;
+            const cpx<T> *src = win + r * plane + (fblk * 4 + fac) * QQ + fatp1 * Q;
 #pragma unroll
             for (int tp2 = 0; tp2 < Q; ++tp2) nx[tp2] = src[tp2];
         };
-        if (active) load_row(0);
+        if (factive) load_row(0);
         for (int r = 0; r < nrhs; ++r) {
             // first pass with the prefactor: Y[a2][c][t'1][t2] =
             //   sum_t'2 M_a2[t'2][t2] conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t'
-            if (active) {
+            if (factive) {
                 cpx<T> acc[Q];
 #pragma unroll
                 for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
@@ -494,13 +505,13 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
                 for (int tp2 = 0; tp2 < Q; ++tp2) {
                     const cpx<T> vv = cmulc(nx[tp2], Ep[tp2]);
 #pragma unroll
-                    for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Ms[a2c][tp2][tt], vv);
+                    for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Mg[(fa2 * Q + tp2) * Q + tt], vv);
                 }
 #pragma unroll
-                for (int tt = 0; tt < Q; ++tt) Y[bbl][a2c][ac][atp1 * Q + tt] = acc[tt];
+                for (int tt = 0; tt < Q; ++tt) Y[fb][fa2][fac][fatp1 * Q + tt] = acc[tt];
             }
             __syncthreads();
-            if (active && r + 1 < nrhs) load_row(r + 1);
+            if (factive && r + 1 < nrhs) load_row(r + 1);
             if (active) {
                 cpx<T> out[H1];
 #pragma unroll
