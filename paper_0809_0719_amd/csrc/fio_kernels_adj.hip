@@ -95,10 +95,19 @@ __global__ __launch_bounds__(NT) void k_term_adj(Geom g, PhaseDev ph, Tables tb,
 //   delta^{A_p B_c}_t' = E(x^{A_p}_t', p0(B_c)) sum_j sum_t M_j1[t'1][t1] M_j2[t'2][t2]
 //                          conj E(x^{A_j}_t, p0(B_c)) delta^{A_j B}_t
 // First pass: thread (j1, c2, t1, j2) forms row t1 of conj E delta for its
-// child (j1, j2) and both c1, contracts over t2 with M_j2, and the two j2
-// partial rows are added through a lane exchange.  Second pass: thread
-// (c, t'2, half) contracts over t1 with M_j1, sums j1 and applies the factor
+// child (j1, j2) and both c1 and contracts over t2 with M_j2; the partial
+// rows of the two j2 are summed.  Second pass: thread (c, t'2, half)
+// contracts over t1 with M_j1, sums j1 and applies the factor
 // E(x^{A_p}_t', p0(B_c)).
+// SPLIT (FP32): j2 is the same for a pair of waves (threads [128 j2,
+// 128 j2 + 128)), so the first-pass factors are wave-uniform (SGPR
+// operands); both partial rows go to LDS and the second pass adds them.
+// Otherwise (FP64, whose doubled partial rows would not fit the LDS budget):
+// the two j2 of a row are adjacent lanes and add their rows through a DPP
+// lane exchange before one of them stores the sum.
+template <typename T, int Q>
+constexpr bool xadj_split() { return sizeof(T) == 4; }
+
 template <typename T, int Q, bool HOIST>
 __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables tb, int level,
                                                    const cpx<T> *__restrict__ win,
@@ -106,10 +115,12 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
                                                    int nrhs, size_t plane) {
     constexpr int QQ = Q * Q;
     constexpr int TPB = 8 * Q;
-    constexpr int BPW = blocks_per_wg<T, Q, 8>();
+    constexpr bool SPLIT = xadj_split<T, Q>();
+    constexpr int NS = SPLIT ? 2 : 1;
+    constexpr int BPW = blocks_per_wg<T, Q, 8 * NS>();
     constexpr int H1 = (Q + 1) / 2;
     __shared__ T Ms[2][Q][Q];                       // Ms[a][t'][t] = M_a[t'][t]
-    __shared__ cpx<T> Y[BPW][2][4][QQ];             // [j1][c][t1][t'2]
+    __shared__ cpx<T> Y[BPW][NS][2][4][QQ];         // [j2 partial][j1][c][t1][t'2]
     __shared__ double sp[BPW][2][Q], cp[BPW][2][Q];
     __shared__ double sj[BPW][2][2][Q], cj[BPW][2][2][Q];
     __shared__ double r0c[BPW][2], ct0[BPW][2], st0[BPW][2];
@@ -153,26 +164,54 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
         }
     }
     __syncthreads();
-    // rr = ((j1 * 2 + c2) * Q + t1) * 2 + j2: the two j2 of a row are adjacent lanes
-    const int j2 = rr & 1, k1 = rr >> 1;
-    const int t1 = k1 % Q, jc = k1 / Q, c2f = jc & 1, j1 = jc >> 1;
-    // second pass: thread (c, t'2, half)
+    // first-pass item (block fb, j1, c2f, t1, j2)
+    int fb, j1, c2f, t1, j2;
+    if constexpr (SPLIT) {
+        j2 = __builtin_amdgcn_readfirstlane(tid / (NT / 2));
+        const int fi = tid - j2 * (NT / 2);
+        fb = fi / (4 * Q);
+        const int fk = fi - fb * (4 * Q);
+        j1 = fk / (2 * Q);
+        c2f = (fk / Q) & 1;
+        t1 = fk % Q;
+    } else {
+        // rr = ((j1 * 2 + c2) * Q + t1) * 2 + j2: the two j2 of a row are adjacent lanes
+        fb = bbl;
+        j2 = rr & 1;
+        const int k1 = rr >> 1;
+        t1 = k1 % Q;
+        const int jc = k1 / Q;
+        c2f = jc & 1;
+        j1 = jc >> 1;
+    }
+    const size_t fblk = (size_t)blockIdx.x * BPW + fb;
+    const bool factive = fb < BPW && fblk < nblk;
+    uint32_t fmB = 0, fmAp = 0;
+    int fap1 = 0, fap2 = 0;
+    if (factive) {
+        fmB = (uint32_t)(fblk & (nBl - 1));
+        fmAp = (uint32_t)(fblk >> (2 * lB));
+        morton_decode(fmAp, fap1, fap2);
+    }
+    // second pass: thread (c, t'2, half) of its block
     const int c = rr / (2 * Q), k2 = rr - c * 2 * Q;
     const int h = k2 / Q, tp2 = k2 - h * Q;
     const int c1 = c >> 1, c2 = c & 1;
     // exponentials shared by all right-hand sides
     cpx<T> E1[2][Q], E2[H1];
-    if (HOIST && active) {
-        const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
-        const double xa1 = box_node(a1, level, tb.z[t1]);
+    auto row_exp = [&](int t2, cpx<T> &e0, cpx<T> &e1) {
+        const int a1 = 2 * fap1 + j1, a2 = 2 * fap2 + j2;
+        const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[t2]),
+                                 sj[fb][0][j1][t1], cj[fb][0][j1][t1], sj[fb][1][j2][t2], cj[fb][1][j2][t2]);
+        const double G = phase_dir(xp, ct0[fb][c2f], st0[fb][c2f]);
+        e0 = cis<T>(r0c[fb][0] * G);
+        e1 = cis<T>(r0c[fb][1] * G);
+    };
+    if (HOIST && factive) {
 #pragma unroll
-        for (int t2 = 0; t2 < Q; ++t2) {
-            const XP xp = make_xp_sc(ph, xa1, box_node(a2, level, tb.z[t2]), sj[bbl][0][j1][t1],
-                                     cj[bbl][0][j1][t1], sj[bbl][1][j2][t2], cj[bbl][1][j2][t2]);
-            const double G = phase_dir(xp, ct0[bbl][c2f], st0[bbl][c2f]);
-            E1[0][t2] = cis<T>(r0c[bbl][0] * G);
-            E1[1][t2] = cis<T>(r0c[bbl][1] * G);
-        }
+        for (int t2 = 0; t2 < Q; ++t2) row_exp(t2, E1[0][t2], E1[1][t2]);
+    }
+    if (HOIST && active) {
         const double xa2 = box_node(ap2, level - 1, tb.z[tp2]);
 #pragma unroll
         for (int kk = 0; kk < H1; ++kk) {
@@ -185,25 +224,23 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
     // inputs of the thread's row, loaded one right-hand side ahead
     cpx<T> nx[Q];
     auto load_row = [&](int r) {
-        const cpx<T> *src = win + r * plane + ((size_t)(4 * mAp + 2 * j1 + j2) * nBl + mB) * QQ + t1 * Q;
+        const cpx<T> *src = win + r * plane + ((size_t)(4 * fmAp + 2 * j1 + j2) * nBl + fmB) * QQ + t1 * Q;
 #pragma unroll
         for (int t2 = 0; t2 < Q; ++t2) nx[t2] = src[t2];
     };
     constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
-    if (PF && active) load_row(0);
+    if (PF && factive) load_row(0);
     for (int r = 0; r < (HOIST ? nrhs : 1); ++r) {
         {
             cpx<T> acc0[Q], acc1[Q];   // c1 = 0, 1
 #pragma unroll
             for (int t = 0; t < Q; ++t) acc0[t] = acc1[t] = {(T)0, (T)0};
-            if (active) {
+            if (factive) {
                 if (!PF) load_row(r);
                 cpx<T> in[Q];
 #pragma unroll
                 for (int k = 0; k < Q; ++k) in[k] = nx[k];
                 if (PF && r + 1 < nrhs) load_row(r + 1);
-                const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
-                const double xa1 = box_node(a1, level, tb.z[t1]);
 #pragma unroll
                 for (int t2 = 0; t2 < Q; ++t2) {
                     cpx<T> e0, e1;
@@ -211,36 +248,42 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
                         e0 = E1[0][t2];
                         e1 = E1[1][t2];
                     } else {
-                        const XP xp = make_xp_sc(ph, xa1, box_node(a2, level, tb.z[t2]), sj[bbl][0][j1][t1],
-                                                 cj[bbl][0][j1][t1], sj[bbl][1][j2][t2], cj[bbl][1][j2][t2]);
-                        const double G = phase_dir(xp, ct0[bbl][c2f], st0[bbl][c2f]);
-                        e0 = cis<T>(r0c[bbl][0] * G);
-                        e1 = cis<T>(r0c[bbl][1] * G);
+                        row_exp(t2, e0, e1);
                     }
                     const cpx<T> d = in[t2];
                     const cpx<T> v0 = cmulc(d, e0);
                     const cpx<T> v1 = cmulc(d, e1);
 #pragma unroll
                     for (int p2 = 0; p2 < Q; ++p2) {
-                        const T m = Ms[j2][p2][t2];
+                        const T m = SPLIT ? Mg[(j2 * Q + p2) * Q + t2] : Ms[j2][p2][t2];
                         crfma(acc0[p2], m, v0);
                         crfma(acc1[p2], m, v1);
                     }
                 }
             }
-            // add the partner lane's (other j2) partial rows
+            if constexpr (SPLIT) {
+                if (factive) {
 #pragma unroll
-            for (int t = 0; t < Q; ++t) {
-                acc0[t].re += swap_adjacent_lanes(acc0[t].re);
-                acc0[t].im += swap_adjacent_lanes(acc0[t].im);
-                acc1[t].re += swap_adjacent_lanes(acc1[t].re);
-                acc1[t].im += swap_adjacent_lanes(acc1[t].im);
-            }
-            if (active && j2 == 0) {
+                    for (int p2 = 0; p2 < Q; ++p2) {
+                        Y[fb][j2][j1][c2f][t1 * Q + p2] = acc0[p2];        // c = 2*0 + c2
+                        Y[fb][j2][j1][2 + c2f][t1 * Q + p2] = acc1[p2];    // c = 2*1 + c2
+                    }
+                }
+            } else {
+                // add the partner lane's (other j2) partial rows
 #pragma unroll
-                for (int p2 = 0; p2 < Q; ++p2) {
-                    Y[bbl][j1][c2f][t1 * Q + p2] = acc0[p2];        // c = 2*0 + c2
-                    Y[bbl][j1][2 + c2f][t1 * Q + p2] = acc1[p2];    // c = 2*1 + c2
+                for (int t = 0; t < Q; ++t) {
+                    acc0[t].re += swap_adjacent_lanes(acc0[t].re);
+                    acc0[t].im += swap_adjacent_lanes(acc0[t].im);
+                    acc1[t].re += swap_adjacent_lanes(acc1[t].re);
+                    acc1[t].im += swap_adjacent_lanes(acc1[t].im);
+                }
+                if (factive && j2 == 0) {
+#pragma unroll
+                    for (int p2 = 0; p2 < Q; ++p2) {
+                        Y[fb][0][j1][c2f][t1 * Q + p2] = acc0[p2];
+                        Y[fb][0][j1][2 + c2f][t1 * Q + p2] = acc1[p2];
+                    }
                 }
             }
         }
@@ -253,7 +296,14 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
             for (int jj1 = 0; jj1 < 2; ++jj1) {
                 cpx<T> col[Q];
 #pragma unroll
-                for (int tt = 0; tt < Q; ++tt) col[tt] = Y[bbl][jj1][c][tt * Q + tp2];
+                for (int tt = 0; tt < Q; ++tt) {
+                    col[tt] = Y[bbl][0][jj1][c][tt * Q + tp2];
+                    if constexpr (SPLIT) {
+                        const cpx<T> o = Y[bbl][NS - 1][jj1][c][tt * Q + tp2];
+                        col[tt].re += o.re;
+                        col[tt].im += o.im;
+                    }
+                }
 #pragma unroll
                 for (int kk = 0; kk < H1; ++kk) {
                     const int tp1 = min(h * H1 + kk, Q - 1);
@@ -683,7 +733,7 @@ static hipError_t xlevel_adj_t(const Geom &g, const PhaseDev &ph, const Tables &
     const unsigned nblk = 1u << (2 * g.L - 2);
 #define L_XLA(Q)                                                                                     \
     {                                                                                                \
-        constexpr int BPW = blocks_per_wg<T, Q, 8>();                                                \
+        constexpr int BPW = blocks_per_wg<T, Q, 8 * (xadj_split<T, Q>() ? 2 : 1)>();               \
         const dim3 grid((nblk + BPW - 1) / BPW);                                                     \
         if (nrhs == 1)                                                                               \
             hipLaunchKernelGGL((k_xlevel_adj<T, Q, false>), grid, dim3(NT), 0, st, g, ph, tb, level, \
