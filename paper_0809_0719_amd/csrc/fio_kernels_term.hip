@@ -142,6 +142,15 @@ __global__ __launch_bounds__(NT) void k_term_b(Geom g, PhaseDev ph, Tables tb, c
     const int m = bx.m, np = bx.np;
     term_setup<T, Q>(g, ph, tb, bx, sx1, cx1, sx2, cx2, Ts, xg);
     const int j1 = lane / m, j2 = lane - (lane / m) * m;
+    // the rows of T this lane uses: pass 1 items i = lane + 64 k all have
+    // j2 = lane % m (m divides 64), pass 2 is the lane's own grid point
+    __syncthreads();
+    T t_p1[Q], t_p2[Q];
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+        t_p1[t] = Ts[j2][t];
+        t_p2[t] = lane < np ? Ts[j1][t] : (T)0;
+    }
 
     // a wave's weights of one right-hand side and chunk, loaded one
     // right-hand side ahead
@@ -184,7 +193,7 @@ __global__ __launch_bounds__(NT) void k_term_b(Geom g, PhaseDev ph, Tables tb, c
                     const int b = i / (Q * m), rr = i - b * (Q * m), t1 = rr / m, jj2 = rr - t1 * m;
                     cpx<T> y = {(T)0, (T)0};
 #pragma unroll
-                    for (int t2 = 0; t2 < Q; ++t2) crfma(y, Ts[jj2][t2], vw[wv][b][t1 * Q + t2]);
+                    for (int t2 = 0; t2 < Q; ++t2) crfma(y, t_p1[t2], vw[wv][b][t1 * Q + t2]);
                     Yw[wv][b][t1 * m + jj2] = y;
                 }
                 wave_sync();
@@ -192,7 +201,7 @@ __global__ __launch_bounds__(NT) void k_term_b(Geom g, PhaseDev ph, Tables tb, c
                     for (int b = 0; b < nb; ++b) {
                         cpx<T> U = {(T)0, (T)0};
 #pragma unroll
-                        for (int t1 = 0; t1 < Q; ++t1) crfma(U, Ts[j1][t1], Yw[wv][b][t1 * m + j2]);
+                        for (int t1 = 0; t1 < Q; ++t1) crfma(U, t_p2[t1], Yw[wv][b][t1 * m + j2]);
                         cfma(acc[k], Ex[b][lane], U);
                     }
                 }
