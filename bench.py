@@ -83,10 +83,13 @@ def lane_ops(kind: str, N: int, q: int, s: int, nrhs: int, rc_switch: int = 8, r
         per_rhs = nA * n2 * (PHS + EXP + CMUL + (q * q + q) * CRMAC) + nA * (n2 / nA) * q * q * (EXP + CMUL)
         return nrhs * per_rhs
     if kind in ("term", "term_adj"):
-        # per (A, B): q^2 prefactors, the two 1-D passes, m^2 factors E(x, p0(B))
+        # per (A, B): q^2 prefactors, the two 1-D passes, m^2 factors E(x, p0(B));
+        # their kernel values (q^2 + m^2 phases and exponentials) once per
+        # launch when several right-hand sides share them
         pairs = n2
-        per_pair = q * q * (PHS + EXP + CMUL) + (q * q * m + m * m * q) * CRMAC + m * m * (PHS + EXP + CMUL)
-        return nrhs * pairs * per_pair
+        shared = (q * q + m * m) * (PHS + EXP)
+        per_rhs = q * q * CMUL + (q * q * m + m * m * q) * CRMAC + m * m * CMUL
+        return pairs * (shared * (1 if nrhs > 1 else nrhs) + nrhs * per_rhs)
     raise ValueError(kind)
 
 
