@@ -32,6 +32,13 @@
  * Thread-safety: distinct plans may be used concurrently; one plan owns one
  * workspace, so concurrent applies on the same plan must be serialised by
  * the caller (e.g. by issuing them on one stream).
+ *
+ * Graph capture: fio_apply and fio_apply_adjoint only launch kernels on the
+ * given stream (no allocation, memset or synchronisation), so a capture of
+ * them into a HIP graph replays the pass.  The replay uses the phase that
+ * was current at capture time.  fio_apply_dphase allocates its tangent
+ * workspace on its first call when nrhs_max < 3; call it once before
+ * capturing it.
  */
 #ifndef FIO_H
 #define FIO_H
