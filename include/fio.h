@@ -182,6 +182,30 @@ int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, void *s
 int fio_apply_dphase(fio_plan_t plan, const void *f, void *u, void *du_da1, void *du_da2, int nrhs,
                      void *stream);
 
+/* Variable amplitude (eq:allfio) through a separated approximation
+ *     a(x,k) = sum_{t < rank} g_t(x) h_t(k)       (end of Sec. 4):
+ *   fio_apply_amplitude:         u = sum_t g_t . B(h_t . f)
+ *                                  ~ sum_k a(x,k) exp(2 pi i Phi(x,k)) f(k),
+ *   fio_apply_amplitude_adjoint: f = sum_t conj(h_t) . B^H(conj(g_t) . u)
+ *                                  ~ sum_x conj(a(x,k)) exp(-2 pi i Phi(x,k)) u(x)
+ * ('.' is the elementwise product).  The rank butterfly applications run
+ * as right-hand sides of one batched apply (chunks of nrhs_max), sharing
+ * every kernel value, as the end of Sec. 4 recommends.
+ *   f, u: device, N x N complex (plan dtype), layouts as fio_apply; the input
+ *         is read only, the output fully overwritten and must not overlap
+ *         the inputs.
+ *   g: device, rank x N x N complex, g[t][i1][i2] = g_t(i1/N, i2/N).
+ *   h: device, rank x N x N complex, h[t][k1+N/2][k2+N/2] = h_t(k).
+ *   1 <= rank <= 4096.
+ * Workspace: two buffers of rank N^2 complex values, allocated by the plan
+ * on first use and regrown (after a device synchronisation) when a larger
+ * rank comes; FIO_ENOMEM if that fails.  Asynchronous on `stream` otherwise;
+ * FIO_EINVAL before any launch on bad arguments. */
+int fio_apply_amplitude(fio_plan_t plan, const void *f, const void *g, const void *h, int rank, void *u,
+                        void *stream);
+int fio_apply_amplitude_adjoint(fio_plan_t plan, const void *u, const void *g, const void *h, int rank,
+                                void *f, void *stream);
+
 /* Diagnostics: run the forward pipeline for one right-hand side up to and
  * including stage `stage` and copy that stage's weights to `weights`.
  *   stage 0                 : initialisation, level s

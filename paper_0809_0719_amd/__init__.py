@@ -43,7 +43,8 @@ _LIB_PATH = os.path.join(_HERE, "libfio.so")
 EXPORTED_SYMBOLS = (
     "fio_plan", "fio_plan_ex", "fio_set_phase", "fio_plan_get_info", "fio_apply",
     "fio_apply_adjoint", "fio_debug_stage", "fio_destroy", "fio_last_error",
-    "fio_profile_enable", "fio_profile_read", "fio_apply_dphase",
+    "fio_profile_enable", "fio_profile_read", "fio_apply_dphase", "fio_apply_amplitude",
+    "fio_apply_amplitude_adjoint",
 )
 
 # kernel kinds of fio_profile_read (FIO_K_* in include/fio.h)
@@ -105,6 +106,8 @@ def load_library():
     lib.fio_apply.argtypes = [vp, vp, vp, i, vp]
     lib.fio_apply_adjoint.argtypes = [vp, vp, vp, i, vp]
     lib.fio_apply_dphase.argtypes = [vp, vp, vp, vp, vp, i, vp]
+    lib.fio_apply_amplitude.argtypes = [vp, vp, vp, vp, i, vp, vp]
+    lib.fio_apply_amplitude_adjoint.argtypes = [vp, vp, vp, vp, i, vp, vp]
     lib.fio_debug_stage.argtypes = [vp, vp, i, vp, vp]
     lib.fio_destroy.argtypes = [vp]
     lib.fio_profile_enable.argtypes = [vp, i]
@@ -235,6 +238,40 @@ class Plan:
         _check(load_library().fio_apply_dphase(self._h, f.data_ptr(), None if u is None else u.data_ptr(),
                                                d1.data_ptr(), d2.data_ptr(), nrhs, st), "fio_apply_dphase")
         return u, d1, d2
+
+    def _prep_factors(self, g: torch.Tensor, h: torch.Tensor):
+        g, rg = self._prep(g, "g")
+        h, rh = self._prep(h, "h")
+        if rg != rh or rg < 1:
+            raise ValueError(f"g and h must hold the same number (>= 1) of factors, got {rg} and {rh}")
+        return g, h, rg
+
+    def apply_amplitude(self, f: torch.Tensor, g: torch.Tensor, h: torch.Tensor,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+        """u = sum_t g_t . B(h_t . f): the FIO with amplitude a(x,k) = sum_t g_t(x) h_t(k)
+        (g: (rank, N, N) on the x grid, h: (rank, N, N) on the frequency grid, f: (N, N))."""
+        f, nrhs = self._prep(f, "f")
+        if nrhs != 1:
+            raise ValueError("apply_amplitude takes one right-hand side")
+        g, h, rank = self._prep_factors(g, h)
+        u = torch.empty_like(f) if out is None else out
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().fio_apply_amplitude(self._h, f.data_ptr(), g.data_ptr(), h.data_ptr(), rank,
+                                                  u.data_ptr(), st), "fio_apply_amplitude")
+        return u
+
+    def adjoint_amplitude(self, u: torch.Tensor, g: torch.Tensor, h: torch.Tensor,
+                          out: torch.Tensor | None = None) -> torch.Tensor:
+        """f = sum_t conj(h_t) . B^H(conj(g_t) . u): the adjoint of apply_amplitude."""
+        u, nrhs = self._prep(u, "u")
+        if nrhs != 1:
+            raise ValueError("adjoint_amplitude takes one right-hand side")
+        g, h, rank = self._prep_factors(g, h)
+        f = torch.empty_like(u) if out is None else out
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().fio_apply_amplitude_adjoint(self._h, u.data_ptr(), g.data_ptr(), h.data_ptr(),
+                                                          rank, f.data_ptr(), st), "fio_apply_amplitude_adjoint")
+        return f
 
     def debug_stage(self, f: torch.Tensor, stage: int) -> torch.Tensor:
         """Weights after forward stage ``stage`` (layout in include/fio.h)."""

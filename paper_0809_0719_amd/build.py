@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libfio.so")
 
 SOURCES = ["fio_plan.cpp", "fio_kernels_fwd.hip", "fio_kernels_adj.hip", "fio_kernels_init.hip", "fio_kernels_term.hip",
            "fio_kernels_mfma.hip",
-           "fio_kernels_tan.hip"]
+           "fio_kernels_tan.hip", "fio_kernels_amp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

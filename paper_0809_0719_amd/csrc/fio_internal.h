@@ -1,7 +1,7 @@
 // Internal definitions shared by the host plan (fio_plan.cpp) and the HIP
 // kernels (fio_kernels_fwd.hip, fio_kernels_adj.hip, fio_kernels_init.hip,
-// fio_kernels_term.hip, fio_kernels_mfma.hip, fio_kernels_tan.hip).  Not part
-// of the public ABI.
+// fio_kernels_term.hip, fio_kernels_mfma.hip, fio_kernels_tan.hip,
+// fio_kernels_amp.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -98,6 +98,14 @@ hipError_t launch_term_batch(int dtype, const Geom &g, const PhaseDev &ph, const
                              void *u, int nrhs, size_t plane, size_t uplane, hipStream_t st);
 hipError_t launch_term_adj_batch(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, const void *u,
                                  void *w_out, int nrhs, size_t plane, size_t uplane, hipStream_t st);
+
+// Elementwise steps of the separated-amplitude applies (fio_kernels_amp.hip):
+// scale:   out[t][i] = op(a[t][i]) b[i];   combine: out[i] = sum_t op(a[t][i]) b[t][i],
+// op = conj if `conj`, t < rank, i < n.
+hipError_t launch_scale_planes(int dtype, bool conj, const void *a, const void *b, void *out, size_t n, int rank,
+                               hipStream_t st);
+hipError_t launch_combine_planes(int dtype, bool conj, const void *a, const void *b, void *out, size_t n, int rank,
+                                 hipStream_t st);
 
 // Adjoint launchers: exact conjugate transposes of the above.
 hipError_t launch_term_adj(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb,

@@ -1,8 +1,8 @@
 // Host side of the C ABI: argument validation, the plan (trees of Sec. 4
 // step 1, interpolation tables, workspace), and the level schedule that
 // drives the kernels of fio_kernels_fwd.hip, fio_kernels_adj.hip,
-// fio_kernels_init.hip, fio_kernels_term.hip, fio_kernels_mfma.hip and
-// fio_kernels_tan.hip.
+// fio_kernels_init.hip, fio_kernels_term.hip, fio_kernels_mfma.hip,
+// fio_kernels_tan.hip and fio_kernels_amp.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -96,6 +96,8 @@ struct fio_plan_s {
     bool init_mm = false;               // initialisation on the matrix cores
     void *ktab = nullptr, *etab = nullptr;
     bool etab_ok = false;               // etab holds the kernel values of the current phase
+    void *amp0 = nullptr, *amp1 = nullptr;  // separated-amplitude workspace, amp_cap planes each
+    int amp_cap = 0;
     void *dtab = nullptr;    // tables
     int32_t *d_idx = nullptr, *d_off = nullptr;
     double2 *d_p = nullptr;
@@ -119,6 +121,8 @@ void free_plan(fio_plan_s *p) {
     (void)hipFree(p->t1);
     (void)hipFree(p->ktab);
     (void)hipFree(p->etab);
+    (void)hipFree(p->amp0);
+    (void)hipFree(p->amp1);
     (void)hipFree(p->dtab);
     (void)hipFree(p->d_idx);
     (void)hipFree(p->d_off);
@@ -586,6 +590,80 @@ int fio_apply_dphase(fio_plan_t plan, const void *f, void *u, void *du_da1, void
                          (char *)du_da1 + r * step, (char *)du_da2 + r * step, st);
         if (rc) return rc;
     }
+    return FIO_OK;
+}
+
+// Workspace of the separated-amplitude applies: two buffers of `rank`
+// planes of N^2 complex values, grown on demand.
+static int ensure_amp(fio_plan_t p, int rank) {
+    if (rank <= p->amp_cap) return FIO_OK;
+    const size_t bytes = (size_t)rank * p->N * p->N * (p->dtype == FIO_C128 ? 16 : 8);
+    if (p->amp0) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(p->amp0);
+        (void)hipFree(p->amp1);
+        p->total_bytes -= 2 * (size_t)p->amp_cap * p->N * p->N * (p->dtype == FIO_C128 ? 16 : 8);
+        p->amp0 = p->amp1 = nullptr;
+        p->amp_cap = 0;
+    }
+    int rc;
+    if ((rc = dmalloc(&p->amp0, bytes, &p->total_bytes, "amplitude workspace 0")) ||
+        (rc = dmalloc(&p->amp1, bytes, &p->total_bytes, "amplitude workspace 1"))) {
+        (void)hipFree(p->amp0);
+        p->amp0 = nullptr;
+        return rc;
+    }
+    p->amp_cap = rank;
+    return FIO_OK;
+}
+
+static int amp_args(fio_plan_t plan, const void *in, const void *g, const void *h, int rank, void *out) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!in || !g || !h || !out) return fail(FIO_EINVAL, "all array arguments must be non-NULL device pointers");
+    if (rank < 1 || rank > 4096) return fail(FIO_EINVAL, "rank must be in [1, 4096] (got %d)", rank);
+    if (in == out || g == out || h == out) return fail(FIO_EINVAL, "the output must not overlap the inputs");
+    if ((rc = set_device(plan))) return rc;
+    return ensure_amp(plan, rank);
+}
+
+int fio_apply_amplitude(fio_plan_t plan, const void *f, const void *g, const void *h, int rank, void *u,
+                        void *stream) {
+    g_last_error.clear();
+    int rc = amp_args(plan, f, g, h, rank, u);
+    if (rc) return rc;
+    const size_t n2 = (size_t)plan->N * plan->N, step = n2 * (plan->dtype == FIO_C128 ? 16 : 8);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_scale_planes(plan->dtype, false, h, f, plan->amp0, n2, rank, st);
+    if (e != hipSuccess) return hip_fail(e, "amplitude scale launch");
+    for (int r = 0; r < rank; r += plan->nrhs_max) {
+        const int nr = std::min(plan->nrhs_max, rank - r);
+        rc = run_forward(plan, (const char *)plan->amp0 + r * step, (char *)plan->amp1 + r * step, nr, -1,
+                         nullptr, st);
+        if (rc) return rc;
+    }
+    e = launch_combine_planes(plan->dtype, false, g, plan->amp1, u, n2, rank, st);
+    if (e != hipSuccess) return hip_fail(e, "amplitude combine launch");
+    return FIO_OK;
+}
+
+int fio_apply_amplitude_adjoint(fio_plan_t plan, const void *u, const void *g, const void *h, int rank, void *f,
+                                void *stream) {
+    g_last_error.clear();
+    int rc = amp_args(plan, u, g, h, rank, f);
+    if (rc) return rc;
+    const size_t n2 = (size_t)plan->N * plan->N, step = n2 * (plan->dtype == FIO_C128 ? 16 : 8);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_scale_planes(plan->dtype, true, g, u, plan->amp0, n2, rank, st);
+    if (e != hipSuccess) return hip_fail(e, "amplitude scale launch");
+    for (int r = 0; r < rank; r += plan->nrhs_max) {
+        const int nr = std::min(plan->nrhs_max, rank - r);
+        rc = run_adjoint(plan, (const char *)plan->amp0 + r * step, (char *)plan->amp1 + r * step, nr, st);
+        if (rc) return rc;
+    }
+    e = launch_combine_planes(plan->dtype, true, h, plan->amp1, f, n2, rank, st);
+    if (e != hipSuccess) return hip_fail(e, "amplitude combine launch");
     return FIO_OK;
 }
 

@@ -1,0 +1,135 @@
+"""Variable amplitude through a separated approximation a(x,k) = sum_t g_t(x)
+h_t(k) (eq:allfio, end of Sec. 4): fio_apply_amplitude and its adjoint
+against the FP64 oracle's per-term reduction sum_t g_t . B(h_t . f) on the
+oracle butterfly (the reduction itself is pinned to the dense eq:allfio sum
+on the CPU).  Tolerances as for the unit-amplitude parity tests: the factors
+enter through exact-order elementwise products and one sum over t."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import amplitude as A
+from oracle import direct as D
+from oracle.butterfly import ButterflyModel
+from workloads import white_noise
+
+from gpu_helpers import rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 2e-5
+
+
+def _factors(N, rank, seed):
+    """Smooth complex factors on the x grid (g) and the frequency grid (h)."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(N)
+    x1, x2 = np.meshgrid(i / N, i / N, indexing="ij")
+    k1, k2 = np.meshgrid(i - N // 2, i - N // 2, indexing="ij")
+    g = np.empty((rank, N, N), complex)
+    h = np.empty((rank, N, N), complex)
+    for t in range(rank):
+        c = rng.standard_normal(6)
+        g[t] = (1 + 0.5 * c[0] * x1 + c[1] * x2 ** 2) * np.exp(1j * (c[2] * x1 - x2))
+        h[t] = 1 / (1 + 0.1 * (c[3] * k1 / N) ** 2 + (k2 / N + c[4]) ** 2) * np.exp(1j * c[5] * k1 / N)
+    return g, h
+
+
+def _dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def _plan(N, q, ph, dtype, nrhs_max):
+    import paper_0809_0719_amd as fio
+    return fio.Plan(N, q, fio.Phase(ph.kind, ph.a1, ph.a2, ph.eta1, ph.eta2), dtype=dtype, nrhs_max=nrhs_max)
+
+
+# (N, q, phase, rank, nrhs_max): rank below, equal to and above the batch size
+CASES = [
+    (32, 7, D.Phase(a1=1.1, a2=0.9, eta1=0.2), 3, 4),
+    (64, 9, D.Phase(), 5, 2),                       # chunks of 2, 2, 1; s = 3 path
+    (16, 5, D.Phase(kind=D.FOURIER), 1, 1),
+]
+
+
+def _ids(c):
+    N, q, ph, rank, nb = c
+    return f"N{N}-q{q}-kind{ph.kind}-rank{rank}-nb{nb}"
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, FP64_TOL), (torch.complex64, FP32_TOL)])
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_amplitude_forward_and_adjoint_match_oracle(case, dtype, tol):
+    N, q, ph, rank, nb = case
+    g, h = _factors(N, rank, 1)
+    f, v = white_noise(N, 2), white_noise(N, 3)
+    model = ButterflyModel(N, q, ph)
+    u_ref = A.separated_forward(model, f, g, h)
+    f_ref = A.separated_adjoint(model, v, g, h)
+    plan = _plan(N, q, ph, dtype, nb)
+    gd, hd = _dev(g, dtype), _dev(h, dtype)
+    u = plan.apply_amplitude(_dev(f, dtype), gd, hd).cpu().numpy()
+    fa = plan.adjoint_amplitude(_dev(v, dtype), gd, hd).cpu().numpy()
+    e = [rel_l2(u, u_ref), rel_max(u, u_ref), rel_l2(fa, f_ref), rel_max(fa, f_ref)]
+    print(f"amplitude {case} {dtype}: forward l2 {e[0]:.2e} max {e[1]:.2e}, adjoint l2 {e[2]:.2e} max {e[3]:.2e}")
+    assert e[0] <= tol and e[2] <= tol
+    assert e[1] <= 4 * tol and e[3] <= 4 * tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-13), (torch.complex64, 1e-6)])
+def test_unit_amplitude_equals_plain_apply(dtype, tol):
+    N, q = 64, 9
+    plan = _plan(N, q, D.Phase(a1=1.05, a2=0.95), dtype, 1)
+    f = _dev(white_noise(N, 4), dtype)
+    one = torch.ones((1, N, N), dtype=dtype, device="cuda")
+    assert rel_max(plan.apply_amplitude(f, one, one).cpu().numpy(), plan.apply(f).cpu().numpy()) <= tol
+    assert rel_max(plan.adjoint_amplitude(f, one, one).cpu().numpy(), plan.adjoint(f).cpu().numpy()) <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
+def test_amplitude_dot_product_identity(dtype, tol):
+    N, q, rank = 32, 6, 4
+    plan = _plan(N, q, D.Phase(a1=0.9, a2=1.2, eta2=0.3), dtype, 3)
+    g, h = _factors(N, rank, 5)
+    gd, hd = _dev(g, dtype), _dev(h, dtype)
+    f, v = _dev(white_noise(N, 6), dtype), _dev(white_noise(N, 7), dtype)
+    lhs = torch.vdot(v.flatten(), plan.apply_amplitude(f, gd, hd).flatten()).item()
+    rhs = torch.vdot(plan.adjoint_amplitude(v, gd, hd).flatten(), f.flatten()).item()
+    print(f"<v, A f> = {lhs}, <A^H v, f> = {rhs}")
+    assert abs(lhs - rhs) <= tol * abs(lhs)
+
+
+def test_amplitude_workspace_regrows_and_is_reused():
+    """Ranks 2, 7, 3 on one plan (the workspace grows once, then is reused):
+    every result equals the same call on a fresh plan."""
+    N, q, ph, dtype = 32, 7, D.Phase(), torch.complex64
+    plan = _plan(N, q, ph, dtype, 2)
+    f = _dev(white_noise(N, 8), dtype)
+    for rank in (2, 7, 3):
+        g, h = _factors(N, rank, 10 + rank)
+        gd, hd = _dev(g, dtype), _dev(h, dtype)
+        u = plan.apply_amplitude(f, gd, hd)
+        u_fresh = _plan(N, q, ph, dtype, 2).apply_amplitude(f, gd, hd)
+        assert torch.equal(u, u_fresh), rank
+
+
+def test_amplitude_bad_arguments():
+    import paper_0809_0719_amd as fio
+    N, dtype = 16, torch.complex64
+    plan = _plan(N, 5, D.Phase(), dtype, 1)
+    f = _dev(white_noise(N, 1), dtype)
+    g = torch.ones((2, N, N), dtype=dtype, device="cuda")
+    with pytest.raises(ValueError):
+        plan.apply_amplitude(f, g, g[:1])
+    with pytest.raises(ValueError):
+        plan.apply_amplitude(torch.stack([f, f]), g, g)
+    lib = fio.load_library()
+    u = torch.empty_like(f)
+    for rank in (0, -1, 4097):
+        assert lib.fio_apply_amplitude(plan._h, f.data_ptr(), g.data_ptr(), g.data_ptr(), rank, u.data_ptr(),
+                                       None) == -1
+    assert lib.fio_apply_amplitude(plan._h, f.data_ptr(), None, g.data_ptr(), 1, u.data_ptr(), None) == -1
+    assert lib.fio_apply_amplitude_adjoint(plan._h, f.data_ptr(), g.data_ptr(), None, 1, u.data_ptr(), None) == -1
+    # output aliasing an input is rejected
+    assert lib.fio_apply_amplitude(plan._h, f.data_ptr(), g.data_ptr(), g.data_ptr(), 1, f.data_ptr(), None) == -1
