@@ -78,6 +78,16 @@ template <typename T>
 constexpr int swadj_rc() { return sizeof(T) == 4 ? 4 : 2; }
 
 
+// Workgroup barrier that orders LDS accesses only: global loads still in
+// flight stay in flight across it (__syncthreads also waits for them), so a
+// register prefetch may be issued anywhere.  For kernels whose threads do
+// not exchange data through global memory within the workgroup.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // The value of the neighbouring lane (lane ^ 1), through a DPP quad
 // permutation [1,0,3,2] on the vector ALU (no LDS-pipe shuffle).
 __device__ __forceinline__ float swap_adjacent_lanes(float x) {

@@ -266,10 +266,9 @@ def test_batched_equals_one_by_one(case, dtype):
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
 def test_batched_termination_more_than_64_rhs(dtype):
-    """The batched termination and its adjoint hold 16 right-hand sides per
-    wave and pass (64 per workgroup); 70 right-hand sides take a second,
-    ragged pass.  Against one-at-a-time applies (N = 64, s = 3: every grid
-    point of a box A is a lane)."""
+    """70 right-hand sides: the one-lane-per-RHS termination kernels take
+    them in two groups of 64 lanes, the second ragged.  Against one-at-a-time
+    applies (N = 64, s = 3: 8 grid columns over 5 waves)."""
     import paper_0809_0719_amd as fio
     N, q = 64, 5
     one = fio.Plan(N, q, fio.Phase(), dtype=dtype)
@@ -282,3 +281,33 @@ def test_batched_termination_more_than_64_rhs(dtype):
         e1 = rel_l2(U[r].cpu().numpy(), one.apply(F[r]).cpu().numpy())
         e2 = rel_l2(G[r].cpu().numpy(), one.adjoint(U[r]).cpu().numpy())
         assert e1 <= tol and e2 <= tol, (r, e1, e2)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("N,q,s", [(64, 9, 3), (32, 5, 2), (32, 3, 1), (16, 4, 0), (64, 12, 3), (64, 8, 3)])
+def test_wide_batched_termination(N, q, s, dtype):
+    """Batches of 32 or more right-hand sides take the one-lane-per-RHS
+    termination kernels where they fit (complex64 q <= 12, complex128
+    q <= 8; the others keep the 16-per-wave kernels): 40 right-hand sides
+    leave 24 lanes idle.  Every s from 0 to 3 (2^s grid columns, fewer or
+    more than the q waves).  Against one-at-a-time applies, and one
+    right-hand side against the oracle."""
+    import paper_0809_0719_amd as fio
+    nr = 40
+    ph = D.Phase(a1=1.1, a2=0.95)
+    phase = fio.Phase(ph.kind, ph.a1, ph.a2)
+    one = fio.Plan(N, q, phase, s=s, dtype=dtype)
+    many = fio.Plan(N, q, phase, s=s, dtype=dtype, nrhs_max=nr)
+    F = _dev(white_noise(N, 80, nrhs=nr), dtype)
+    U = many.apply(F)
+    G = many.adjoint(U)
+    tol = 1e-13 if dtype == torch.complex128 else 2e-6
+    for r in (0, 17, 39):
+        e1 = rel_l2(U[r].cpu().numpy(), one.apply(F[r]).cpu().numpy())
+        e2 = rel_l2(G[r].cpu().numpy(), one.adjoint(U[r]).cpu().numpy())
+        assert e1 <= tol and e2 <= tol, (r, e1, e2)
+    f39 = white_noise(N, 80, nrhs=nr)[39]
+    u_ref = ButterflyModel(N, q, ph, s=s).apply(f39)
+    e = rel_l2(U[39].cpu().numpy(), u_ref)
+    print(f"wide termination N={N} q={q} s={s} {dtype}: rhs 39 vs oracle {e:.2e}")
+    assert e <= (FP64_TOL if dtype == torch.complex128 else FP32_TOL)
