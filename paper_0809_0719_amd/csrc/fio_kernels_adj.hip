@@ -62,12 +62,12 @@ __global__ __launch_bounds__(NT) void k_term_adj(Geom g, PhaseDev ph, Tables tb,
             ctb[tid] = c_;
             stb[tid] = s_;
         }
-        __syncthreads();
+        lds_barrier();
         for (int i = tid; i < nb * np; i += NT) {
             const int b = i / np;
             U[b * np + jp] = cmulc(uv, cis<T>(r0b[b] * phase_dir(xg, ctb[b], stb[b])));
         }
-        __syncthreads();
+        lds_barrier();
         // Y[b][t1][j2] = sum_j1 Tt[j1][t1] U[b][j1][j2]
         for (int i = tid; i < nb * Q * m; i += NT) {
             const int b = i / (Q * m), r = i - b * (Q * m);
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(NT) void k_term_adj(Geom g, PhaseDev ph, Tables tb,
             for (int jj1 = 0; jj1 < m; ++jj1) crfma(acc, Tt[jj1 * Q + t1], U[b * np + jj1 * m + jj2]);
             Y[i] = acc;
         }
-        __syncthreads();
+        lds_barrier();
         // delta[b][t1][t2] = E(x^A_t, p0(B)) sum_j2 Tt[j2][t2] Y[b][t1][j2]
         for (int i = tid; i < nb * QQ; i += NT) {
             const int b = i / QQ, t = i - b * QQ;
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(NT) void k_term_adj(Geom g, PhaseDev ph, Tables tb,
                                      sx1[t1], cx1[t1], sx2[t2], cx2[t2]);
             dst[(size_t)(b0 + b) * QQ + t] = cmul(acc, cis<T>(r0b[b] * phase_dir(xp, ctb[b], stb[b])));
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
             st0[bbl][c] = s_;
         }
     }
-    __syncthreads();
+    lds_barrier();
     // first-pass item (block fb, j1, c2f, t1, j2)
     int fb, j1, c2f, t1, j2;
     if constexpr (SPLIT) {
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         if (active) {
             cpx<T> acc[H1];
 #pragma unroll
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -414,10 +414,10 @@ __global__ __launch_bounds__(NT) void k_switch_adj(Geom g, PhaseDev ph, Tables t
         cpx<T> pre[LPT];
 #pragma unroll
         for (int k = 0; k < LPT; ++k) pre[k] = {(T)0, (T)0};
-        __syncthreads();  // the previous chunk's readers are done with rowbuf
+        lds_barrier();  // the previous chunk's readers are done with rowbuf
         fetch(0, pre);
         stash(0, pre);
-        __syncthreads();
+        lds_barrier();
 
         cpx<T> P[RC][HH], Qs[RC][HH], Mi[RC];
 #pragma unroll
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(NT) void k_switch_adj(Geom g, PhaseDev ph, Tables t
                 }
             }
             if (t1 + 1 < Q) stash(buf ^ 1, pre);
-            __syncthreads();
+            lds_barrier();
         }
         // every read of this chunk happened before the barrier above
         if (active) {
@@ -532,14 +532,14 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
             stb[bbl][rr] = s_;
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (active) {
         const int a1 = 2 * ap1 + (j >> 1), a2 = 2 * ap2 + (j & 1);
         const XP xp = make_xp(ph, box_centre(a1, level), box_centre(a2, level));
         Gc[bbl][j][rr] = phase_dir(xp, ctc[bbl][rr], stc[bbl][rr]);
         if (rr < Q) Gb[bbl][j][rr] = phase_dir(xp, ctb[bbl][rr], stb[bbl][rr]);
     }
-    __syncthreads();
+    lds_barrier();
     // first pass: the child index c2 is the same for a pair of waves (threads
     // [128 c2, 128 c2 + 128)), row (block, j, t1) within it, so the factors
     // M_c2[t2][t'2] are wave-uniform (scalar operands); second pass: thread
@@ -598,9 +598,9 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
 #pragma unroll
             for (int p2 = 0; p2 < Q; ++p2) Y[fb][fj][fc2][t1 * Q + p2] = acc[p2];
         }
-        __syncthreads();
+        lds_barrier();
         // the next right-hand side's row is loaded during the (longer) second
-        // pass (a barrier waits for every outstanding load)
+        // pass (issuing it before the first pass measured slower)
         if (PF && factive && ri + 1 < nrhs) load_row(ri + 1);
         if (active) {
             cpx<T> acc[H1];
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
                 if (tp1 < Q) dst[tp1 * Q + tp2] = acc[kk];
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -663,7 +663,7 @@ __global__ __launch_bounds__(NT) void k_init_adj(Geom g, PhaseDev ph, Tables tb,
         ctb[tid] = c_;
         stb[tid] = s_;
     }
-    __syncthreads();
+    lds_barrier();
     const int beg = src.off[mB], end = src.off[mB + 1];
     for (int c0 = beg; c0 < end; c0 += NT) {
         const int jsrc = c0 + tid;
@@ -682,13 +682,13 @@ __global__ __launch_bounds__(NT) void k_init_adj(Geom g, PhaseDev ph, Tables tb,
         cpx<T> out = {(T)0, (T)0};
         for (int a0 = 0; a0 < nA; a0 += ACH2) {
             const int na = min(ACH2, nA - a0);
-            __syncthreads();
+            lds_barrier();
             if (tid < na) {
                 int a1, a2;
                 morton_decode((uint32_t)(a0 + tid), a1, a2);
                 xA[tid] = make_xp(ph, box_centre(a1, g.s), box_centre(a2, g.s));
             }
-            __syncthreads();
+            lds_barrier();
             for (int i = tid; i < na * QQ; i += NT) {
                 const int al = i / QQ, t = i - al * QQ;
                 const int t1 = t / Q, t2 = t - t1 * Q;
@@ -696,7 +696,7 @@ __global__ __launch_bounds__(NT) void k_init_adj(Geom g, PhaseDev ph, Tables tb,
                 const cpx<T> e = cis<T>(rho * phase_dir(xA[al], ctb[t2], stb[t2]));
                 gA[al][t] = cmul(win[((size_t)(a0 + al) * nBl + mB) * QQ + t], e);
             }
-            __syncthreads();
+            lds_barrier();
             if (has) {
                 for (int al = 0; al < na; ++al) {
                     cpx<T> sacc = {(T)0, (T)0};

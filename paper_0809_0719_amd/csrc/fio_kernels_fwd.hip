@@ -65,7 +65,7 @@ __global__ __launch_bounds__(NT) void k_init(Geom g, PhaseDev ph, Tables tb, Sou
     for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
 
     const int beg = src.off[mB], end = src.off[mB + 1];
-    __syncthreads();
+    lds_barrier();
     for (int c0 = beg; c0 < end; c0 += SCH) {
         const int n = min(SCH, end - c0);
         if (tid < n) {
@@ -79,14 +79,14 @@ __global__ __launch_bounds__(NT) void k_init(Geom g, PhaseDev ph, Tables tb, Sou
             kk[tid] = make_double2((double)(idx / g.N - g.N / 2), (double)(idx % g.N - g.N / 2));
             fs[tid] = f[idx];
         }
-        __syncthreads();
+        lds_barrier();
         // kernel values E(x0(A), k) f(k) for this chunk, all A of the workgroup
         for (int it = tid; it < nAc * n; it += NT) {
             const int al = it / n, jj = it - al * n;
             const cpx<T> e = cis<T>(phase_cart(xA[al], kk[jj].x, kk[jj].y));
             gA[al][jj] = cmul(e, fs[jj]);
         }
-        __syncthreads();
+        lds_barrier();
         if (active) {
             for (int jj = 0; jj < n; ++jj) {
                 const cpx<T> gv = gA[aL][jj];
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(NT) void k_init(Geom g, PhaseDev ph, Tables tb, Sou
                 for (int t2 = 0; t2 < Q; ++t2) crfma(acc[t2], lag2[jj][t2], h);
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     if (!active) return;
     // remodulation conj E(x0(A), p^B_t) and store
@@ -180,14 +180,14 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
             stb[bbl][rr] = s_;
         }
     }
-    __syncthreads();
+    lds_barrier();
     const int a1 = 2 * ap1 + (j >> 1), a2 = 2 * ap2 + (j & 1);
     if (active) {
         const XP xp = make_xp(ph, box_centre(a1, level), box_centre(a2, level));
         Gc[bbl][j][rr] = phase_dir(xp, ctc[bbl][rr], stc[bbl][rr]);
         if (rr < Q) Gb[bbl][j][rr] = phase_dir(xp, ctb[bbl][rr], stb[bbl][rr]);
     }
-    __syncthreads();
+    lds_barrier();
     // exponentials of this thread's row (first pass) and column (second
     // pass), shared by all right-hand sides
     const int c1 = rr / Q, tp1 = rr - c1 * Q;
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
 #pragma unroll
             for (int tt = 0; tt < Q; ++tt) W[bbl][j][rr * Q + tt] = acc[tt];
         }
-        __syncthreads();
+        lds_barrier();
         if (active) {
             // second pass: column t2, rows t1 of one half, then remodulation
             cpx<T> col[2 * Q];
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_switch(Geom g, PhaseDev ph, Tables tb, c
 
     for (int r0 = 0; r0 < (ONE ? 1 : nrhs); r0 += RC) {
         const int nr = min(RC, nrhs - r0);
-        __syncthreads();
+        lds_barrier();
         // pair sums / differences of rows j and q-1-j (thread (t1, t2): t1 plays j)
         if (active) {
             for (int rc = 0; rc < nr; ++rc) {
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(NT) void k_switch(Geom g, PhaseDev ph, Tables tb, c
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         if (!active) continue;
         const double r0v = rho0[pl];
         cpx<T> acc[RC];
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
             st0[bbl][c] = s_;
         }
     }
-    __syncthreads();
+    lds_barrier();
     // exponentials shared by all right-hand sides: the prefactor row (c, t'1)
     // of threads rr < 4q, and the remodulation E(x^A_t, p0(B_c)) of the
     // second-pass column (A, t2, half) of every thread
@@ -485,8 +485,8 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
         }
     }
     if constexpr (HOIST) {
-        // inputs of the first-pass row, loaded one right-hand side ahead (during
-        // the second pass: a barrier waits for every outstanding load)
+        // inputs of the first-pass row, loaded one right-hand side ahead, during
+        // the second pass (issuing it before the first pass measured slower)
         cpx<T> nx[Q];
         auto load_row = [&](int r) {
             const cpx<T> *src = win + r * plane + (fblk * 4 + fac) * QQ + fatp1 * Q;
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
 #pragma unroll
                 for (int tt = 0; tt < Q; ++tt) Y[fb][fa2][fac][fatp1 * Q + tt] = acc[tt];
             }
-            __syncthreads();
+            lds_barrier();
             if (factive && r + 1 < nrhs) load_row(r + 1);
             if (active) {
                 cpx<T> out[H1];
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
                     if (t1 < Q) dst[t1 * Q + t2] = out[kk];
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
         return;
     }
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
 #pragma unroll
         for (int tp2 = 0; tp2 < Q; ++tp2) v[bbl][pc][ptp1 * Q + tp2] = cmulc(src[tp2], pre_exp(tp2));
     }
-    __syncthreads();
+    lds_barrier();
     // first pass (second dimension): Y[a2][c][t'1][t2] = sum_t'2 M_a2[t'2][t2] v[c][t'1][t'2]
     if (active) {
         cpx<T> acc[Q];
@@ -563,7 +563,7 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
 #pragma unroll
         for (int tt = 0; tt < Q; ++tt) Y[bbl][a2c][ac][atp1 * Q + tt] = acc[tt];
     }
-    __syncthreads();
+    lds_barrier();
     // second pass (first dimension), remodulation E(x^A_t, p0(B_c)), sum over c
     if (active) {
         cpx<T> out[H1];
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(NT) void k_term(Geom g, PhaseDev ph, Tables tb,
             ctb[tid] = c_;
             stb[tid] = s_;
         }
-        __syncthreads();
+        lds_barrier();
         // prefactor conj E(x^A_t, p0(B)) delta^{AB}_t
         for (int i = tid; i < nb * QQ; i += NT) {
             const int b = i / QQ, t = i - b * QQ;
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(NT) void k_term(Geom g, PhaseDev ph, Tables tb,
             const cpx<T> e = cis<T>(r0b[b] * phase_dir(xp, ctb[b], stb[b]));
             v[i] = cmulc(src[(size_t)(b0 + b) * QQ + t], e);
         }
-        __syncthreads();
+        lds_barrier();
         // pass 1 (second dimension): Y[b][t1][j2] = sum_t2 Tt[j2][t2] v[b][t1][t2]
         for (int i = tid; i < nb * Q * m; i += NT) {
             const int b = i / (Q * m), r = i - b * (Q * m);
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(NT) void k_term(Geom g, PhaseDev ph, Tables tb,
             for (int t2 = 0; t2 < Q; ++t2) crfma(acc, Tt[jj2 * Q + t2], vv[t2]);
             Y[i] = acc;
         }
-        __syncthreads();
+        lds_barrier();
         // pass 2 (first dimension) and the factor E(x, p0(B)), summed per grid point
         for (int i = tid; i < nb * np; i += NT) {
             const int b = i / np;  // i % np == jp since NT % np == 0
@@ -696,10 +696,10 @@ __global__ __launch_bounds__(NT) void k_term(Geom g, PhaseDev ph, Tables tb,
             for (int t1 = 0; t1 < Q; ++t1) crfma(acc, Tt[j1 * Q + t1], yy[t1 * m]);
             cfma(uacc, cis<T>(r0b[b] * phase_dir(xg, ctb[b], stb[b])), acc);
         }
-        __syncthreads();
+        lds_barrier();
     }
     red[tid] = uacc;
-    __syncthreads();
+    lds_barrier();
     if (tid < np) {
         cpx<T> sum = red[tid];
         for (int k = tid + np; k < NT; k += np) {

@@ -57,14 +57,14 @@ __device__ __forceinline__ void init_mm_setup(const Geom &g, const PhaseDev &ph,
         morton_decode((uint32_t)tid, a1, a2);
         xA[tid] = make_xp(ph, box_centre(a1, g.s), box_centre(a2, g.s));
     }
-    __syncthreads();
+    lds_barrier();
     for (int i = tid; i < IM_NA * QQ; i += NT) {
         const int a = i / QQ, t = i - a * QQ, t1 = t / Q, t2 = t - t1 * Q;
         double st, ct;
         sincospi(2.0 * box_node(bp2, lB, zs[t2]), &st, &ct);
         Er[a][t] = cis<float>(g.rho_scale * box_node(bp1, lB, zs[t1]) * phase_dir(xA[a], ct, st));
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // K[j][t] = L_t1(u1(p_j)) L_t2(u2(p_j)) for the j-th source in sorted order
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(NT) void k_init_etab(Geom g, PhaseDev ph, const int
         morton_decode((uint32_t)tid, a1, a2);
         xA[tid] = make_xp(ph, box_centre(a1, g.s), box_centre(a2, g.s));
     }
-    __syncthreads();
+    lds_barrier();
     const int A = tid & (IM_NA - 1);
     for (int jl = tid >> 6; jl < 64; jl += NT / IM_NA) {
         const int j = blockIdx.x * 64 + jl;
@@ -326,9 +326,9 @@ __global__ __launch_bounds__(NT, 2) void k_init_adj_mm(Geom g, PhaseDev ph, Tabl
         }
         if (np > 0) fetch(0);
         for (int c0 = 0; c0 < np; c0 += 16) {
-            __syncthreads();  // the previous tile's readers of Kc, Es and part are finished
+            lds_barrier();  // the previous tile's readers of Kc, Es and part are finished
             stash(c0);
-            __syncthreads();
+            lds_barrier();
             if (c0 + 16 < np) fetch(c0 + 16);
             f32x4 acc[CTW];
 #pragma unroll
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(NT, 2) void k_init_adj_mm(Geom g, PhaseDev ph, Tabl
             sacc.re += __shfl_xor(sacc.re, 32);
             sacc.im += __shfl_xor(sacc.im, 32);
             if (kq == 0) part[wv][cl] = sacc;
-            __syncthreads();
+            lds_barrier();
             if (tid < 16 && c0 + tid < np) {
                 cpx<float> v = part[0][tid];
 #pragma unroll

@@ -109,7 +109,7 @@ __device__ __forceinline__ void term_chunk(const Geom &g, const PhaseDev &ph, co
         ctb[tid] = c_;
         stb[tid] = s_;
     }
-    __syncthreads();
+    lds_barrier();
     between();
     for (int i = tid; i < nb * QQ; i += NT) {
         const int b = i / QQ, t = i - b * QQ, t1 = t / Q, t2 = t - t1 * Q;
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(NT) void k_term_b(Geom g, PhaseDev ph, Tables tb, c
     const int j1 = lane / m, j2 = lane - (lane / m) * m;
     // the rows of T this lane uses: pass 1 items i = lane + 64 k all have
     // j2 = lane % m (m divides 64), pass 2 is the lane's own grid point
-    __syncthreads();
+    lds_barrier();
     T t_p1[Q], t_p2[Q];
 #pragma unroll
     for (int t = 0; t < Q; ++t) {
@@ -172,11 +172,11 @@ __global__ __launch_bounds__(NT) void k_term_b(Geom g, PhaseDev ph, Tables tb, c
         for (int k = 0; k < TRW; ++k) acc[k] = {(T)0, (T)0};
         for (int b0 = 0; b0 < bx.nBt; b0 += BC) {
             const int nb = min(BC, bx.nBt - b0);
-            __syncthreads();  // set-up done; the previous chunk's readers are finished
+            lds_barrier();  // set-up done; the previous chunk's readers are finished
             term_chunk<T, Q, BC>(g, ph, tb, bx, b0, nb, sx1, cx1, sx2, cx2, xg, r0b, ctb, stb, Epre, Ex, [&]() {
                 if (rp + wv < nrhs) load(rp + wv, b0, nb);
             });
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int k = 0; k < TRW; ++k) {
                 const int r = rp + k * TW + wv;
@@ -254,9 +254,9 @@ __global__ __launch_bounds__(NT) void k_term_adj_b(Geom g, PhaseDev ph, Tables t
         }
         for (int b0 = 0; b0 < bx.nBt; b0 += BC) {
             const int nb = min(BC, bx.nBt - b0);
-            __syncthreads();
+            lds_barrier();
             term_chunk<T, Q, BC>(g, ph, tb, bx, b0, nb, sx1, cx1, sx2, cx2, xg, r0b, ctb, stb, Epre, Ex, []() {});
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int k = 0; k < TRW; ++k) {
                 const int r = rp + k * TW + wv;
