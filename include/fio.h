@@ -206,6 +206,64 @@ int fio_apply_amplitude(fio_plan_t plan, const void *f, const void *g, const voi
 int fio_apply_amplitude_adjoint(fio_plan_t plan, const void *u, const void *g, const void *h, int rank,
                                 void *f, void *stream);
 
+/* ---- uneven batches ------------------------------------------------------
+ * A batch applies several plans (any N, q, phase, dtype) as one unit, the
+ * mixed-size workload of many small and large problems: fio_batch_apply
+ * forks from `stream` onto the batch's internal streams (events only, no
+ * host synchronisation), runs each plan's fio_apply there -- the largest work
+ * (N^2 q^3) first, each on the stream with the least work so far -- and
+ * joins back into `stream`, so problems too small to fill the device run
+ * side by side.  Since the fork and the join are events, a stream capture of
+ * fio_batch_apply records the whole batch as one HIP graph (call it once
+ * before capturing: plans make their initialisation tables on first use).
+ *   plans:    host array of n distinct plans on one device.  The batch keeps
+ *             the handles, not copies: destroy the batch before its plans,
+ *             and do not use a plan elsewhere while a batch apply that
+ *             includes it may be running.
+ *   1 <= n <= 4096; 1 <= nstreams <= 16 (internal streams, default priority).
+ *   f, u:     host arrays of n device pointers; f[i], u[i] are plan i's input
+ *             and output for one right-hand side, laid out as for fio_apply.
+ * FIO_EINVAL before any launch on bad arguments. */
+typedef struct fio_batch_s *fio_batch_t;
+int fio_batch_create(const fio_plan_t *plans, int n, int nstreams, fio_batch_t *out);
+int fio_batch_apply(fio_batch_t batch, const void *const *f, void *const *u, void *stream);
+int fio_batch_apply_adjoint(fio_batch_t batch, const void *const *u, void *const *f, void *stream);
+int fio_batch_destroy(fio_batch_t batch);
+
+/* Direct evaluation of eq:dfio at sampled targets, by the definition:
+ *     out[i] = sum_k exp(2 pi i Phi(x_i, k)) f(k),  x_i = (r / N, r % N) / N,
+ * r = rows[i], with the plan's N, phase and dtype.  Phases, exponentials and
+ * sums are FP64 whatever the dtype (the output is stored in the plan dtype).
+ * This is the reference of the error measure eq:err (Sec. 5) on a sample of
+ * targets; it costs nrows N^2 phase evaluations.
+ *   f:    device, N x N complex (plan dtype), as for fio_apply.
+ *   rows: device, nrows int64 flat target indices i1 N + i2 in [0, N^2) (an
+ *         index outside that range evaluates a point outside X; no memory is
+ *         addressed by it).
+ *   out:  device, nrows complex (plan dtype).
+ *   1 <= nrows <= 2^20.  Asynchronous on `stream`. */
+int fio_direct_rows(fio_plan_t plan, const void *f, const int64_t *rows, int nrows, void *out, void *stream);
+
+/* Choice of q by the estimated error (Sec. 5: q is raised until the error
+ * estimate is small enough).  For q = qmin, qmin + 1, ..., qmax: builds a
+ * plan (N, phase and opts as given), applies it to the probe
+ *     f(k) = exp(2 pi i v_k),  v_k = (SplitMix64(seed, k) >> 11) 2^-53,
+ * with k the flat index k1' N + k2' (k' = k + N/2), and estimates eq:err
+ * against fio_direct_rows on nrows targets rows[i] = SplitMix64(seed ^
+ * 0x5851F42D4C957F2D, i) mod N^2, where SplitMix64(s, i) is the output of the
+ * generator of Steele, Lea and Flood (2014) with state s + (i + 1) 0x9E3779B97F4A7C15.
+ * Stops at the first q whose estimate is <= tol.
+ *   q_out, err_out: host; the chosen q and its estimate.  When no q reaches
+ *                   tol they receive qmax and its estimate (compare *err_out
+ *                   with tol).
+ *   errs:           host array of qmax - qmin + 1 doubles, or NULL; receives
+ *                   every estimate made (NaN for the q not tried).
+ *   3 <= qmin <= qmax <= 16, tol > 0, 1 <= nrows <= 4096.
+ * Synchronous; allocates and frees its plans and buffers on the current
+ * device (null stream). */
+int fio_select_q(int N, const fio_phase_t *phase, const fio_plan_opts_t *opts, double tol, int qmin, int qmax,
+                 int nrows, uint64_t seed, int *q_out, double *err_out, double *errs);
+
 /* Diagnostics: run the forward pipeline for one right-hand side up to and
  * including stage `stage` and copy that stage's weights to `weights`.
  *   stage 0                 : initialisation, level s

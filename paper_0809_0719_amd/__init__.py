@@ -25,7 +25,8 @@ from dataclasses import dataclass
 import torch
 
 __all__ = [
-    "Phase", "Plan", "FIOApply", "FIOApplyPhase", "fio_apply", "load_library", "library_path",
+    "Phase", "Plan", "Batch", "FIOApply", "FIOApplyPhase", "fio_apply", "direct_rows", "select_q",
+    "load_library", "library_path",
     "FOURIER", "ELLIPSE", "C128", "C64", "EXPORTED_SYMBOLS",
 ]
 
@@ -44,7 +45,8 @@ EXPORTED_SYMBOLS = (
     "fio_plan", "fio_plan_ex", "fio_set_phase", "fio_plan_get_info", "fio_apply",
     "fio_apply_adjoint", "fio_debug_stage", "fio_destroy", "fio_last_error",
     "fio_profile_enable", "fio_profile_read", "fio_apply_dphase", "fio_apply_amplitude",
-    "fio_apply_amplitude_adjoint",
+    "fio_apply_amplitude_adjoint", "fio_batch_create", "fio_batch_apply", "fio_batch_apply_adjoint",
+    "fio_batch_destroy", "fio_direct_rows", "fio_select_q",
 )
 
 # kernel kinds of fio_profile_read (FIO_K_* in include/fio.h)
@@ -109,6 +111,14 @@ def load_library():
     lib.fio_apply_amplitude.argtypes = [vp, vp, vp, vp, i, vp, vp]
     lib.fio_apply_amplitude_adjoint.argtypes = [vp, vp, vp, vp, i, vp, vp]
     lib.fio_debug_stage.argtypes = [vp, vp, i, vp, vp]
+    lib.fio_batch_create.argtypes = [ctypes.POINTER(vp), i, i, ctypes.POINTER(vp)]
+    lib.fio_batch_apply.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.fio_batch_apply_adjoint.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.fio_batch_destroy.argtypes = [vp]
+    lib.fio_direct_rows.argtypes = [vp, vp, vp, i, vp, vp]
+    lib.fio_select_q.argtypes = [i, ctypes.POINTER(_CPhase), ctypes.POINTER(_COpts), ctypes.c_double, i, i, i,
+                                 ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]
     lib.fio_destroy.argtypes = [vp]
     lib.fio_profile_enable.argtypes = [vp, i]
     lib.fio_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i]
@@ -356,3 +366,90 @@ def fio_apply(f: torch.Tensor, plan: Plan, a: torch.Tensor | None = None) -> tor
     if a is None:
         return FIOApply.apply(f, plan)
     return FIOApplyPhase.apply(f, a, plan)
+
+
+class Batch:
+    """Several plans applied as one unit (``fio_batch_create``): each plan's
+    apply runs on one of ``nstreams`` internal streams, forked from and
+    joined back into the current stream, so problems of different sizes run
+    side by side; a stream capture of :meth:`apply` records the whole batch
+    as one graph.  The batch keeps references to its plans."""
+
+    def __init__(self, plans, nstreams: int = 4):
+        self.plans = list(plans)
+        if len({id(p) for p in self.plans}) != len(self.plans):
+            raise ValueError("a plan appears twice in the batch")
+        handles = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(load_library().fio_batch_create(handles, len(self.plans), int(nstreams), ctypes.byref(h)),
+               "fio_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().fio_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _run(self, fn, xs, outs, name):
+        if len(xs) != len(self.plans):
+            raise ValueError(f"need {len(self.plans)} inputs, got {len(xs)}")
+        xs = [p._prep(x, name)[0] for p, x in zip(self.plans, xs)]
+        for p, x in zip(self.plans, xs):
+            if x.numel() != p.N * p.N:
+                raise ValueError(f"{name}: one right-hand side per plan")
+        outs = [torch.empty_like(x) for x in xs] if outs is None else list(outs)
+        n = len(xs)
+        a = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        b = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        st = torch.cuda.current_stream(self.plans[0].device).cuda_stream
+        _check(fn(self._h, a, b, st), name)
+        return outs
+
+    def apply(self, fs, outs=None):
+        """[B_i f_i] for the plans B_i (one (N_i, N_i) input each)."""
+        return self._run(load_library().fio_batch_apply, fs, outs, "fio_batch_apply")
+
+    def adjoint(self, us, outs=None):
+        """[B_i^H u_i]."""
+        return self._run(load_library().fio_batch_apply_adjoint, us, outs, "fio_batch_apply_adjoint")
+
+
+def direct_rows(plan: Plan, f: torch.Tensor, rows: torch.Tensor) -> torch.Tensor:
+    """u(x_r) = sum_k exp(2 pi i Phi(x_r, k)) f(k) for the flat target indices
+    ``rows`` (int64, on the plan's device), FP64 inside (``fio_direct_rows``)."""
+    f, nrhs = plan._prep(f, "f")
+    if nrhs != 1:
+        raise ValueError("direct_rows takes one right-hand side")
+    rows = rows.to(device=plan.device, dtype=torch.int64).contiguous()
+    out = torch.empty(rows.numel(), dtype=plan.dtype, device=plan.device)
+    if rows.numel() == 0:
+        return out
+    st = torch.cuda.current_stream(plan.device).cuda_stream
+    _check(load_library().fio_direct_rows(plan._h, f.data_ptr(), rows.data_ptr(), rows.numel(), out.data_ptr(), st),
+           "fio_direct_rows")
+    return out
+
+
+def select_q(N: int, phase: Phase = Phase(), tol: float = 1e-4, qmin: int = 3, qmax: int = 16,
+             nrows: int = 64, seed: int = 0, s: int | None = None, lm: int | None = None,
+             dtype: torch.dtype = torch.complex64):
+    """The smallest q in [qmin, qmax] whose estimated error eq:err is <= tol
+    (``fio_select_q``).  Returns (q, estimate, {q: estimate for every q tried});
+    when no q reaches tol, q is qmax and its estimate exceeds tol."""
+    opts = _COpts(-1 if s is None else int(s), -1 if lm is None else int(lm),
+                  C64 if dtype == torch.complex64 else C128, 1, CONTRACT_FP)
+    q = ctypes.c_int()
+    err = ctypes.c_double()
+    n = max(qmax - qmin + 1, 1)
+    errs = (ctypes.c_double * n)()
+    _check(load_library().fio_select_q(int(N), ctypes.byref(_cphase(phase)), ctypes.byref(opts), float(tol),
+                                       int(qmin), int(qmax), int(nrows), int(seed) & (2**64 - 1), ctypes.byref(q),
+                                       ctypes.byref(err), errs), "fio_select_q")
+    tried = {qmin + i: errs[i] for i in range(n) if errs[i] == errs[i]}
+    return q.value, err.value, tried

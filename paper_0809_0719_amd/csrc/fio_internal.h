@@ -129,4 +129,22 @@ hipError_t launch_tangent_step(int dtype, int step, const Geom &g, const PhaseDe
                                const Sources &src, int level, const void *in, void *out, size_t plane,
                                void *u1, void *u2, hipStream_t st);
 
+// Direct sum of eq:dfio at listed targets (FP64 phase, exponentials and sums)
+// and the SplitMix64 unit-modulus probe (fio_kernels_direct.hip).
+hipError_t launch_direct_rows(int dtype, int N, const PhaseDev &ph, const void *f, const int64_t *rows, int nrows,
+                              void *out, hipStream_t st);
+hipError_t launch_probe(int dtype, int N, uint64_t seed, void *f, hipStream_t st);
+
+// Host helpers shared by the host sources (defined in fio_plan.cpp): the
+// calling thread's error message, and the parts of a plan other host code
+// needs.
+int set_error(int code, const char *fmt, ...);
+int set_hip_error(hipError_t e, const char *what);
+void clear_error();
+struct PlanView {
+    int N, q, dtype, device;
+    PhaseDev ph;
+};
+int plan_view(fio_plan_t plan, PlanView *v);
+
 }  // namespace fio

@@ -2,7 +2,9 @@
 // step 1, interpolation tables, workspace), and the level schedule that
 // drives the kernels of fio_kernels_fwd.hip, fio_kernels_adj.hip,
 // fio_kernels_init.hip, fio_kernels_term.hip, fio_kernels_mfma.hip,
-// fio_kernels_tan.hip and fio_kernels_amp.hip.
+// fio_kernels_tan.hip and fio_kernels_amp.hip.  Batches of plans, the
+// direct evaluation at sampled targets and the choice of q are in
+// fio_batch.cpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -182,6 +184,35 @@ struct Timed {
 };
 
 }  // namespace
+
+namespace fio {
+
+int set_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int set_hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+
+void clear_error() { g_last_error.clear(); }
+
+int plan_view(fio_plan_t plan, PlanView *v) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    v->N = plan->N;
+    v->q = plan->q;
+    v->dtype = plan->dtype;
+    v->device = plan->device;
+    v->ph = to_dev(&plan->phase);
+    return FIO_OK;
+}
+
+}  // namespace fio
 
 extern "C" {
 

@@ -56,3 +56,30 @@ def mixed_batch(seed: int, n: int = 32) -> list[dict]:
     fseeds = rng.integers(0, 2**31 - 1, size=n)
     return [dict(N=int(Ns[i]), tol=float(tols[i]), eta1=float(etas[i, 0]), eta2=float(etas[i, 1]),
                  f_seed=int(fseeds[i])) for i in range(n)]
+
+
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, k) -> np.ndarray:
+    """Output of the SplitMix64 generator (Steele, Lea and Flood, 2014) at
+    counters k: state seed + (k+1) 0x9E3779B97F4A7C15, then its two
+    xor-shift-multiply rounds and a final xor-shift (uint64 arithmetic)."""
+    k = np.asarray(k, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & _MASK64) + (k + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def probe_phases(N: int, seed: int) -> np.ndarray:
+    """The q selector's probe: f(k) = exp(2 pi i v_k), v_k = (SplitMix64(seed,
+    k) >> 11) 2^-53, k the flat index of (k1 + N/2, k2 + N/2); complex128 (N, N)."""
+    v = (splitmix64(seed, np.arange(N * N)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.exp(2j * np.pi * v).reshape(N, N)
+
+
+def probe_rows(N: int, nrows: int, seed: int) -> np.ndarray:
+    """The q selector's sampled targets: SplitMix64(seed ^ 0x5851F42D4C957F2D, i) mod N^2."""
+    return (splitmix64(seed ^ 0x5851F42D4C957F2D, np.arange(nrows)) % np.uint64(N * N)).astype(np.int64)
