@@ -1,0 +1,82 @@
+"""Pins of the three-dimensional oracle (Sec. 5, eq:ex3): the direct sum
+against the 3-D DFT closed form and hand-computed phases, homogeneity, and
+the butterfly model against the direct sum -- its error falls steadily as q
+grows for both phases and both start offsets, while a planted mistake
+(conjugated switch, transposed child interpolation) keeps it at O(1)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import butterfly3 as B
+
+
+def _noise(N, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((N, N, N)) + 1j * rng.standard_normal((N, N, N))) / np.sqrt(2)
+
+
+def test_direct3_fourier_is_the_dft():
+    N = 8
+    f = _noise(N, 1)
+    u = B.direct3(N, B.FOURIER, f).reshape(N, N, N)
+    ref = N ** 3 * np.fft.ifftn(np.fft.ifftshift(f))
+    assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_phase3_hand_values_and_homogeneity():
+    # x = (1/4, 1/4, 1/4): sin(pi/2)^3 = 1, c = 1; k = (1, 2, 2): |k| = 3
+    assert abs(B.phi3(B.SPHERES, 0.25, 0.25, 0.25, 1.0, 2.0, 2.0) - (1.25 + 3.0)) < 1e-14
+    # x = (0, 0, 0): c = 3/4; k = (3, 0, 4): |k| = 5
+    assert abs(B.phi3(B.SPHERES, 0.0, 0.0, 0.0, 3.0, 0.0, 4.0) - 3.75) < 1e-14
+    rng = np.random.default_rng(2)
+    x, k = rng.uniform(0, 1, 3), rng.normal(size=3)
+    for lam in (0.5, 3.0, 17.0):
+        assert abs(B.phi3(B.SPHERES, *x, *(lam * k)) - lam * B.phi3(B.SPHERES, *x, *k)) < 1e-12 * lam
+
+
+def test_spherical_map_inverts():
+    N = 8
+    k, p = B.spherical_points(N)
+    kk = np.stack(B.k_of_p3(N, *p))
+    assert np.abs(kk - k).max() < 1e-12
+    assert p.min() >= 0.0 and p.max() <= 1.0 + 1e-15
+
+
+def _err(N, q, kind, s, lm, f, model=B.ButterflyModel3):
+    ref = B.direct3(N, kind, f)
+    u = model(N, q, kind, s=s, lm=lm).apply(f).ravel()
+    return float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("kind", [B.FOURIER, B.SPHERES])
+@pytest.mark.parametrize("s", [0, 1])
+def test_model3_error_falls_with_q(kind, s):
+    """N = 8, lm = 1: every step present for s = 0 (p-level 1 is lm, the
+    x-levels 2 and 3); errors about 0.84 / 0.36 / 0.14 (s = 0) and 0.79 /
+    0.33 / 0.13 (s = 1) at q = 3 / 5 / 7."""
+    N = 8
+    f = _noise(N, 3)
+    e = [_err(N, q, kind, s, 1, f) for q in (3, 5, 7)]
+    print(f"kind {kind} s {s}: {e}")
+    assert e[0] > e[1] > e[2] and e[2] < 0.2 and e[1] / e[2] > 2.0
+
+
+class _ConjSwitch(B.ButterflyModel3):
+    def switch(self, d):
+        return np.conj(super().switch(np.conj(d)))
+
+
+class _TransposedChild(B.ButterflyModel3):
+    def child_interp(self):
+        return np.transpose(super().child_interp(), (0, 2, 1))
+
+
+@pytest.mark.parametrize("bad", [_ConjSwitch, _TransposedChild])
+def test_model3_planted_mistakes_are_caught(bad):
+    N, q, kind = 8, 7, B.SPHERES
+    f = _noise(N, 3)
+    good = _err(N, q, kind, 0, 1, f)
+    wrong = _err(N, q, kind, 0, 1, f, model=bad)
+    print(f"{bad.__name__}: {wrong:.3f} vs {good:.3f}")
+    assert wrong > 0.5 and wrong > 3 * good
