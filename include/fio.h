@@ -264,6 +264,32 @@ int fio_direct_rows(fio_plan_t plan, const void *f, const int64_t *rows, int nro
 int fio_select_q(int N, const fio_phase_t *phase, const fio_plan_opts_t *opts, double tol, int qmin, int qmax,
                  int nrows, uint64_t seed, int *q_out, double *err_out, double *errs);
 
+/* ---- three dimensions (Sec. 5, last example) -----------------------------
+ * u(x) = sum_{k in Omega} exp(2 pi i Phi(x,k)) f(k) on X = {i/N}^3,
+ * Omega = {-N/2 <= k_j < N/2}, by the butterfly with q x q x q tensor
+ * Chebyshev grids and octrees (eight children per box), l(A) + l(B) = L.
+ * The frequencies are mapped to spherical coordinates
+ *     p = (|k| / (sqrt(3) N / 2), theta / pi, phi / (2 pi) mod 1),
+ * theta = arccos(k3/|k|), phi = atan2(k2, k1), k = 0 -> p = 0, the analogue
+ * of eq:polar, so that Phi(x, k(p)) = |k| Phi(x, k/|k|) is evaluated from
+ * one direction phase per node.  Forward apply, one right-hand side.
+ *   FIO3_PHASE_FOURIER: Phi = x . k
+ *   FIO3_PHASE_SPHERES: eq:ex3, Phi = x . k + c(x)|k|,
+ *                       c(x) = (3 + sin 2 pi x1 sin 2 pi x2 sin 2 pi x3)/4
+ * fio3_plan: N power of two, 4 <= N <= 256; 3 <= q <= 8; s, lm as in
+ *   fio_plan_opts_t (-1: min(3, L/2) and L/2; s <= lm <= L - s); dtype
+ *   FIO_C64 or FIO_C128.  Holds two weight buffers of N^3 q^3 complex values
+ *   and the sorted sources; FIO_ENOMEM if they do not fit.
+ * fio3_apply: f device N x N x N complex (plan dtype),
+ *   f[k1+N/2][k2+N/2][k3+N/2]; u device N x N x N, u[i1][i2][i3] = u(i/N);
+ *   u must not overlap f.  Asynchronous on `stream`. */
+#define FIO3_PHASE_FOURIER 0
+#define FIO3_PHASE_SPHERES 1
+typedef struct fio3_plan_s *fio3_plan_t;
+int fio3_plan(int N, int q, int phase_kind, int s, int lm, int dtype, fio3_plan_t *out);
+int fio3_apply(fio3_plan_t plan, const void *f, void *u, void *stream);
+int fio3_destroy(fio3_plan_t plan);
+
 /* Diagnostics: run the forward pipeline for one right-hand side up to and
  * including stage `stage` and copy that stage's weights to `weights`.
  *   stage 0                 : initialisation, level s

@@ -25,13 +25,14 @@ from dataclasses import dataclass
 import torch
 
 __all__ = [
-    "Phase", "Plan", "Batch", "FIOApply", "FIOApplyPhase", "fio_apply", "direct_rows", "select_q",
+    "Phase", "Plan", "Plan3", "Batch", "FIOApply", "FIOApplyPhase", "fio_apply", "direct_rows", "select_q",
     "load_library", "library_path",
     "FOURIER", "ELLIPSE", "C128", "C64", "EXPORTED_SYMBOLS",
 ]
 
 FOURIER = 0
 ELLIPSE = 1
+SPHERES = 1  # three-dimensional phase kind of eq:ex3 (Plan3)
 C128 = 0
 C64 = 1
 CONTRACT_FP = 0
@@ -46,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "fio_apply_adjoint", "fio_debug_stage", "fio_destroy", "fio_last_error",
     "fio_profile_enable", "fio_profile_read", "fio_apply_dphase", "fio_apply_amplitude",
     "fio_apply_amplitude_adjoint", "fio_batch_create", "fio_batch_apply", "fio_batch_apply_adjoint",
-    "fio_batch_destroy", "fio_direct_rows", "fio_select_q",
+    "fio_batch_destroy", "fio_direct_rows", "fio_select_q", "fio3_plan", "fio3_apply", "fio3_destroy",
 )
 
 # kernel kinds of fio_profile_read (FIO_K_* in include/fio.h)
@@ -116,6 +117,9 @@ def load_library():
     lib.fio_batch_apply_adjoint.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     lib.fio_batch_destroy.argtypes = [vp]
     lib.fio_direct_rows.argtypes = [vp, vp, vp, i, vp, vp]
+    lib.fio3_plan.argtypes = [i, i, i, i, i, i, ctypes.POINTER(vp)]
+    lib.fio3_apply.argtypes = [vp, vp, vp, vp]
+    lib.fio3_destroy.argtypes = [vp]
     lib.fio_select_q.argtypes = [i, ctypes.POINTER(_CPhase), ctypes.POINTER(_COpts), ctypes.c_double, i, i, i,
                                  ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)]
@@ -453,3 +457,45 @@ def select_q(N: int, phase: Phase = Phase(), tol: float = 1e-4, qmin: int = 3, q
                                        ctypes.byref(err), errs), "fio_select_q")
     tried = {qmin + i: errs[i] for i in range(n) if errs[i] == errs[i]}
     return q.value, err.value, tried
+
+
+class Plan3:
+    """Three-dimensional butterfly plan (``fio3_plan``): N^3 targets and
+    frequencies, q^3 Chebyshev grids, octrees.  kind: FOURIER (x . k) or
+    SPHERES (eq:ex3); s, lm as for :class:`Plan`; dtype complex64 or
+    complex128.  Forward apply only, one right-hand side (N, N, N)."""
+
+    def __init__(self, N: int, q: int, kind: int = SPHERES, s: int | None = None, lm: int | None = None,
+                 dtype: torch.dtype = torch.complex64):
+        lib = load_library()
+        if dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        self.N, self.q, self.kind, self.dtype = int(N), int(q), int(kind), dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        _check(lib.fio3_plan(self.N, self.q, self.kind, -1 if s is None else int(s), -1 if lm is None else int(lm),
+                             C64 if dtype == torch.complex64 else C128, ctypes.byref(h)), "fio3_plan")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().fio3_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, f: torch.Tensor) -> torch.Tensor:
+        """u = B f for f of shape (N, N, N), f[k1+N/2, k2+N/2, k3+N/2]."""
+        if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != self.dtype:
+            raise TypeError(f"f must be a {self.dtype} CUDA (HIP) tensor")
+        if tuple(f.shape) != (self.N,) * 3:
+            raise ValueError(f"f must have shape ({self.N}, {self.N}, {self.N})")
+        f = f.contiguous()
+        u = torch.empty_like(f)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().fio3_apply(self._h, f.data_ptr(), u.data_ptr(), st), "fio3_apply")
+        return u

@@ -135,6 +135,29 @@ hipError_t launch_direct_rows(int dtype, int N, const PhaseDev &ph, const void *
                               void *out, hipStream_t st);
 hipError_t launch_probe(int dtype, int N, uint64_t seed, void *f, hipStream_t st);
 
+// Three dimensions (fio_kernels_3d.hip, host side fio3.cpp).
+struct Geom3 {
+    int N, L, q, s, lm, kind;
+    double rho_scale;  // (sqrt(3)/2) N : |k| = rho_scale * p1
+};
+//   z[q], lam[q]   Chebyshev nodes and barycentric weights 1/prod_{j!=i}(z_i - z_j)
+//   M[2][q][q]     M_c[t][j] = L_t((z_j + c - 1/2)/2), FP64 and FP32
+//   T[2^s][q]      T[j][t] = L_t(j 2^-s - 1/2), FP64 and FP32
+struct Tab3 {
+    const double *z, *lam, *Md, *Td;
+    const float *Mf, *Tf;
+};
+// Sources sorted by their level-(L-s) box: Omega index, p (3 per source), CSR offsets.
+struct Src3 {
+    const int32_t *idx;
+    const double *p;
+    const int32_t *off;
+};
+// step: 0 initialisation (in = f), 1 p-level, 2 switch (in place on out),
+// 3 x-level, 4 termination (out = u).
+hipError_t launch_step3(int dtype, int step, const Geom3 &g, const Tab3 &tb, const Src3 &src, int level,
+                        const void *in, void *out, hipStream_t st);
+
 // Host helpers shared by the host sources (defined in fio_plan.cpp): the
 // calling thread's error message, and the parts of a plan other host code
 // needs.

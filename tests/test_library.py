@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "fio.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fio_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(fio3?_[a-z_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
