@@ -127,6 +127,46 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
 
 
+def bench_3d(N: int, q: int, steps: int, warmup: int, rows: int):
+    """The three-dimensional example (eq:ex3, Table 3 of the numerical
+    section): forward applies of one white-noise input, FP32 weights, FP64
+    phases; eq:err on ``rows`` sampled points against the direct sum."""
+    import torch
+
+    import paper_0809_0719_amd as fio
+    from oracle import butterfly3 as B3
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(7)
+    f_host = (rng.standard_normal((N, N, N)) + 1j * rng.standard_normal((N, N, N))) / np.sqrt(2.0)
+    plan = fio.Plan3(N, q, fio.SPHERES, dtype=torch.complex64)
+    f = torch.as_tensor(f_host).to(torch.complex64).cuda()
+    for _ in range(warmup):
+        u = plan.apply(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u = plan.apply(f)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # CPU baseline leg: the oracle's direct sum (numpy, FP64) at sampled points,
+    # timed and extrapolated to all N^3 points; the same values give eq:err
+    pts = np.sort(np.random.default_rng(107).choice(N ** 3, size=min(rows, N ** 3), replace=False))
+    tc = time.perf_counter()
+    ref = B3.direct3(N, B3.SPHERES, f.cpu().numpy().astype(np.complex128), pts)
+    tcpu = time.perf_counter() - tc
+    got = u.cpu().numpy().ravel()[pts]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    cpu = {"value": len(pts) / (tcpu * N ** 3), "unit": "applies/s", "cores": 1, "kind": "oracle",
+           "sample": f"FP64 direct sum (numpy, phases on one thread) at {len(pts)} of the {N ** 3} points, "
+                     f"{tcpu:.2f} s; "
+                     f"extrapolated x{N ** 3 / len(pts):.0f} to one full apply"}
+    print(json.dumps({"metric": "3-D FIO applies/sec (eq:ex3)", "value": 1.0 / dt, "unit": "applies/s",
+                      "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": dt * 1e3,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+                      "data": "synthetic", "rel_err_vs_direct_sum": err, "cpu_baseline": cpu,
+                      "config": {"workload": f"eq:ex3 3-D N={N} q={q}", "N": N, "q": q}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,11 +181,18 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=3072,
                     help="sampled points of the CPU baseline (about 10 s of the FP64 direct sum)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dims", type=int, choices=[2, 3], default=2,
+                    help="3: the three-dimensional example eq:ex3 (forward applies, --N3, --q3)")
+    ap.add_argument("--N3", type=int, default=64)
+    ap.add_argument("--q3", type=int, default=7)
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.copy_calib:
         copy_calibration()
+        return
+    if args.dims == 3:
+        bench_3d(args.N3, args.q3, args.steps, args.warmup, 64 if args.N3 <= 128 else 16)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -80,7 +80,8 @@ __global__ __launch_bounds__(NT) void k3_init(Geom3 g, Tab3 tb, Src3 src, const 
     __shared__ T lg[3][C3][Q];
     const int tid = threadIdx.x;
     const int lB = g.L - g.s, nA = 1 << g.s, nB = 1 << lB, nB3 = nB * nB * nB;
-    const int pair = blockIdx.x, iA = pair / nB3, iB = pair - iA * nB3;
+    if (linear_block() >= ((size_t)nA * nA * nA) * nB3) return;  // past the pairs (uniform)
+    const int pair = (int)linear_block(), iA = pair / nB3, iB = pair - iA * nB3;
     int a1, a2, a3, b1, b2, b3;
     decode3(iA, nA, a1, a2, a3);
     decode3(iB, nB, b1, b2, b3);
@@ -149,7 +150,8 @@ __global__ __launch_bounds__(NT) void k3_plevel(Geom3 g, Tab3 tb, int level, con
     __shared__ T Ms[2][Q][Q];
     const int tid = threadIdx.x;
     const int lB = g.L - level, nA = 1 << level, nB = 1 << lB, nB3 = nB * nB * nB, nBc = 2 * nB;
-    const int pair = blockIdx.x, iA = pair / nB3, iB = pair - iA * nB3;
+    if (linear_block() >= ((size_t)nA * nA * nA) * nB3) return;  // past the pairs (uniform)
+    const int pair = (int)linear_block(), iA = pair / nB3, iB = pair - iA * nB3;
     int a1, a2, a3, b1, b2, b3;
     decode3(iA, nA, a1, a2, a3);
     decode3(iB, nB, b1, b2, b3);
@@ -207,7 +209,8 @@ __global__ __launch_bounds__(NT) void k3_switch(Geom3 g, Tab3 tb, cpx<T> *__rest
     __shared__ double rhos[Q];
     const int tid = threadIdx.x;
     const int lA = g.lm, lB = g.L - g.lm, nA = 1 << lA, nB = 1 << lB, nB3 = nB * nB * nB;
-    const int pair = blockIdx.x, iA = pair / nB3, iB = pair - iA * nB3;
+    if (linear_block() >= ((size_t)nA * nA * nA) * nB3) return;  // past the pairs (uniform)
+    const int pair = (int)linear_block(), iA = pair / nB3, iB = pair - iA * nB3;
     int a1, a2, a3, b1, b2, b3;
     decode3(iA, nA, a1, a2, a3);
     decode3(iB, nB, b1, b2, b3);
@@ -252,7 +255,8 @@ __global__ __launch_bounds__(NT) void k3_xlevel(Geom3 g, Tab3 tb, int level, con
     __shared__ T Ms[2][Q][Q];
     const int tid = threadIdx.x;
     const int lB = g.L - level, nA = 1 << level, nB = 1 << lB, nB3 = nB * nB * nB, nBc = 2 * nB;
-    const int pair = blockIdx.x, iA = pair / nB3, iB = pair - iA * nB3;
+    if (linear_block() >= ((size_t)nA * nA * nA) * nB3) return;  // past the pairs (uniform)
+    const int pair = (int)linear_block(), iA = pair / nB3, iB = pair - iA * nB3;
     int a1, a2, a3, b1, b2, b3;
     decode3(iA, nA, a1, a2, a3);
     decode3(iB, nB, b1, b2, b3);
@@ -340,7 +344,8 @@ __global__ __launch_bounds__(NT) void k3_term(Geom3 g, Tab3 tb, const cpx<T> *__
     __shared__ T Tm[8][Q];
     const int tid = threadIdx.x;
     const int lA = g.L - g.s, nA = 1 << lA, m = 1 << g.s, nB = 1 << g.s, nB3 = nB * nB * nB, m3 = m * m * m;
-    const int iA = blockIdx.x;
+    if (linear_block() >= (size_t)nA * nA * nA) return;  // past the boxes (uniform)
+    const int iA = (int)linear_block();
     int a1, a2, a3;
     decode3(iA, nA, a1, a2, a3);
     const T *Tt = pick_T3<T>(tb);
@@ -409,26 +414,26 @@ __global__ __launch_bounds__(NT) void k3_term(Geom3 g, Tab3 tb, const cpx<T> *__
 template <typename T>
 static hipError_t step3_t(int step, const Geom3 &g, const Tab3 &tb, const Src3 &src, int level, const void *in,
                           void *out, hipStream_t st) {
-    const unsigned pairs = 1u << (3 * g.L);
+    const size_t pairs = (size_t)1 << (3 * g.L);
 #define L3(Q)                                                                                                     \
     switch (step) {                                                                                               \
         case 0:                                                                                                   \
-            hipLaunchKernelGGL((k3_init<T, Q>), dim3(pairs), dim3(NT), 0, st, g, tb, src, (const cpx<T> *)in,    \
+            hipLaunchKernelGGL((k3_init<T, Q>), grid_of(pairs), dim3(NT), 0, st, g, tb, src, (const cpx<T> *)in,    \
                                (cpx<T> *)out);                                                                    \
             break;                                                                                                \
         case 1:                                                                                                   \
-            hipLaunchKernelGGL((k3_plevel<T, Q>), dim3(pairs), dim3(NT), 0, st, g, tb, level,                    \
+            hipLaunchKernelGGL((k3_plevel<T, Q>), grid_of(pairs), dim3(NT), 0, st, g, tb, level,                    \
                                (const cpx<T> *)in, (cpx<T> *)out);                                                \
             break;                                                                                                \
         case 2:                                                                                                   \
-            hipLaunchKernelGGL((k3_switch<T, Q>), dim3(pairs), dim3(NT), 0, st, g, tb, (cpx<T> *)out);           \
+            hipLaunchKernelGGL((k3_switch<T, Q>), grid_of(pairs), dim3(NT), 0, st, g, tb, (cpx<T> *)out);           \
             break;                                                                                                \
         case 3:                                                                                                   \
-            hipLaunchKernelGGL((k3_xlevel<T, Q>), dim3(pairs), dim3(NT), 0, st, g, tb, level,                    \
+            hipLaunchKernelGGL((k3_xlevel<T, Q>), grid_of(pairs), dim3(NT), 0, st, g, tb, level,                    \
                                (const cpx<T> *)in, (cpx<T> *)out);                                                \
             break;                                                                                                \
         default:                                                                                                  \
-            hipLaunchKernelGGL((k3_term<T, Q>), dim3(1u << (3 * (g.L - g.s))), dim3(NT), 0, st, g, tb,           \
+            hipLaunchKernelGGL((k3_term<T, Q>), grid_of((size_t)1 << (3 * (g.L - g.s))), dim3(NT), 0, st, g, tb,           \
                                (const cpx<T> *)in, (cpx<T> *)out);                                                \
     }
     switch (g.q) {

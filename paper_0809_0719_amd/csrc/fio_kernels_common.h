@@ -78,6 +78,16 @@ template <typename T>
 constexpr int swadj_rc() { return sizeof(T) == 4 ? 4 : 2; }
 
 
+// Grids of more than 2^32 / NT workgroups (the work-item limit of one grid
+// dimension): the workgroups are laid out over (x, y) with x at most 2^16,
+// and kernels take their linear index.  Workgroups past the count the
+// launcher asked for are the kernel's to skip.
+__device__ __forceinline__ size_t linear_block() { return (size_t)blockIdx.y * gridDim.x + blockIdx.x; }
+inline dim3 grid_of(size_t nblocks) {
+    const size_t gx = nblocks < 65536 ? nblocks : 65536;
+    return dim3((unsigned)gx, (unsigned)((nblocks + gx - 1) / gx));
+}
+
 // Workgroup barrier that orders LDS accesses only: global loads still in
 // flight stay in flight across it (__syncthreads also waits for them), so a
 // register prefetch may be issued anywhere.  For kernels whose threads do

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_switch(Geom g, PhaseDev ph, Tables tb, c
     const int tid = threadIdx.x;
     const int pl = tid / QQ, t = tid - pl * QQ;
     const size_t npairs = (size_t)1 << (2 * g.L);
-    const size_t pair = (size_t)blockIdx.x * PPB + pl;
+    const size_t pair = linear_block() * PPB + pl;
     const bool active = (pl < PPB) && (pair < npairs);
     const int lA = g.lm, lB = g.L - g.lm;
     const size_t nBl = (size_t)1 << (2 * lB);
@@ -776,12 +776,11 @@ static hipError_t switch_t(const Geom &g, const PhaseDev &ph, const Tables &tb, 
         constexpr int PPB = NT / (Q * Q);                                                            \
         const unsigned nblk = (unsigned)((npairs + PPB - 1) / PPB);                                  \
         if (nrhs == 1)                                                                               \
-            hipLaunchKernelGGL((k_switch<T, Q, 1, true>), dim3(nblk), dim3(NT), 0, st, g, ph, tb,    \
+            hipLaunchKernelGGL((k_switch<T, Q, 1, true>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, \
                                (cpx<T> *)w, nrhs, plane);                                            \
         else                                                                                         \
-            hipLaunchKernelGGL((k_switch<T, Q, switch_rc<T>(), false>), dim3(nblk), dim3(NT), 0, st,  \
-                               g, ph,                                                                \
-                               tb, (cpx<T> *)w, nrhs, plane);                                        \
+            hipLaunchKernelGGL((k_switch<T, Q, switch_rc<T>(), false>), grid_of(nblk), dim3(NT), 0,  \
+                               st, g, ph, tb, (cpx<T> *)w, nrhs, plane);                             \
     }
     FIO_DISPATCH_Q(g.q, L_SW)
 #undef L_SW

@@ -177,7 +177,7 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
 
     const int tid = threadIdx.x;
     const int lB = g.L - level;
-    const size_t blk = blockIdx.x;
+    const size_t blk = linear_block();  // exact grid: the block count is a power of two
     const size_t nBl = (size_t)1 << (2 * lB);
     const uint32_t mB = (uint32_t)(blk & (nBl - 1));
     const uint32_t mAp = (uint32_t)(blk >> (2 * lB));
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_switch_tan(Geom g, PhaseDev ph, Tables t
     const int tid = threadIdx.x;
     const int pl = tid / QQ, t = tid - pl * QQ;
     const size_t npairs = (size_t)1 << (2 * g.L);
-    const size_t pair = (size_t)blockIdx.x * PPB + pl;
+    const size_t pair = linear_block() * PPB + pl;
     const bool active = (pl < PPB) && (pair < npairs);
     const int lA = g.lm, lB = g.L - g.lm;
     const size_t nBl = (size_t)1 << (2 * lB);
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
 
     const int tid = threadIdx.x;
     const int lB = g.L - level;
-    const size_t blk = blockIdx.x;
+    const size_t blk = linear_block();  // exact grid: the block count is a power of two
     const size_t nBl = (size_t)1 << (2 * lB);
     const uint32_t mB = (uint32_t)(blk & (nBl - 1));
     const uint32_t mAp = (uint32_t)(blk >> (2 * lB));
@@ -660,10 +660,10 @@ static hipError_t tan_t(int step, const Geom &g, const PhaseDev &ph, const Table
         const unsigned nblk = 1u << (2 * g.L - 2);
 #define L_LT(Q)                                                                                          \
     if (step == 1)                                                                                       \
-        hipLaunchKernelGGL((k_plevel_tan<T, Q>), dim3(nblk), dim3(NT), 0, st, g, ph, tb, level,          \
+        hipLaunchKernelGGL((k_plevel_tan<T, Q>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, level,       \
                            (const cpx<T> *)in, (cpx<T> *)out, plane);                                    \
     else                                                                                                 \
-        hipLaunchKernelGGL((k_xlevel_tan<T, Q>), dim3(nblk), dim3(NT), 0, st, g, ph, tb, level,          \
+        hipLaunchKernelGGL((k_xlevel_tan<T, Q>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, level,       \
                            (const cpx<T> *)in, (cpx<T> *)out, plane);
         FIO_DISPATCH_QT(g.q, L_LT)
 #undef L_LT
@@ -672,7 +672,7 @@ static hipError_t tan_t(int step, const Geom &g, const PhaseDev &ph, const Table
 #define L_ST(Q)                                                                                          \
     {                                                                                                    \
         constexpr int PPB = NT / (Q * Q);                                                                \
-        hipLaunchKernelGGL((k_switch_tan<T, Q>), dim3((unsigned)((npairs + PPB - 1) / PPB)), dim3(NT), 0, \
+        hipLaunchKernelGGL((k_switch_tan<T, Q>), grid_of((npairs + PPB - 1) / PPB), dim3(NT), 0,         \
                            st, g, ph, tb, (cpx<T> *)out, plane);                                         \
     }
         FIO_DISPATCH_QT(g.q, L_ST)

@@ -311,3 +311,22 @@ def test_wide_batched_termination(N, q, s, dtype):
     e = rel_l2(U[39].cpu().numpy(), u_ref)
     print(f"wide termination N={N} q={q} s={s} {dtype}: rhs 39 vs oracle {e:.2e}")
     assert e <= (FP64_TOL if dtype == torch.complex128 else FP32_TOL)
+
+
+def test_grid_beyond_2_32_work_items():
+    """N = 4096, q = 12: the switch has one pair per workgroup, 2^24
+    workgroups of 256 threads -- 2^32 work-items, past the limit of one grid
+    dimension, so the launch spreads the workgroups over two.  Checked with
+    the Fourier phase against the closed form N^2 IDFT(ifftshift(f)); the
+    oracle model's error at q = 12 is 7.9e-4 (N = 64) and 9.5e-4 (N = 128),
+    slowly growing with N."""
+    import paper_0809_0719_amd as fio
+    N, q = 4096, 12
+    f = white_noise(N, 9)
+    ref = N * N * np.fft.ifft2(np.fft.ifftshift(f))
+    plan = fio.Plan(N, q, fio.Phase(kind=fio.FOURIER))
+    u = plan.apply(_dev(f, torch.complex64)).cpu().numpy()
+    del plan
+    e = rel_l2(u, ref)
+    print(f"N={N} q={q} Fourier phase vs closed form: {e:.2e}")
+    assert e < 5e-3
