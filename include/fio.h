@@ -288,6 +288,10 @@ int fio_select_q(int N, const fio_phase_t *phase, const fio_plan_opts_t *opts, d
 typedef struct fio3_plan_s *fio3_plan_t;
 int fio3_plan(int N, int q, int phase_kind, int s, int lm, int dtype, fio3_plan_t *out);
 int fio3_apply(fio3_plan_t plan, const void *f, void *u, void *stream);
+/* fio3_apply_adjoint: f = B^H u, the exact conjugate transpose of fio3_apply
+ * (every step transposed, in reverse order); layouts as fio3_apply, f must
+ * not overlap u.  Asynchronous on `stream`. */
+int fio3_apply_adjoint(fio3_plan_t plan, const void *u, void *f, void *stream);
 int fio3_destroy(fio3_plan_t plan);
 
 /* Diagnostics: run the forward pipeline for one right-hand side up to and

@@ -47,7 +47,8 @@ EXPORTED_SYMBOLS = (
     "fio_apply_adjoint", "fio_debug_stage", "fio_destroy", "fio_last_error",
     "fio_profile_enable", "fio_profile_read", "fio_apply_dphase", "fio_apply_amplitude",
     "fio_apply_amplitude_adjoint", "fio_batch_create", "fio_batch_apply", "fio_batch_apply_adjoint",
-    "fio_batch_destroy", "fio_direct_rows", "fio_select_q", "fio3_plan", "fio3_apply", "fio3_destroy",
+    "fio_batch_destroy", "fio_direct_rows", "fio_select_q", "fio3_plan", "fio3_apply", "fio3_apply_adjoint",
+    "fio3_destroy",
 )
 
 # kernel kinds of fio_profile_read (FIO_K_* in include/fio.h)
@@ -119,6 +120,7 @@ def load_library():
     lib.fio_direct_rows.argtypes = [vp, vp, vp, i, vp, vp]
     lib.fio3_plan.argtypes = [i, i, i, i, i, i, ctypes.POINTER(vp)]
     lib.fio3_apply.argtypes = [vp, vp, vp, vp]
+    lib.fio3_apply_adjoint.argtypes = [vp, vp, vp, vp]
     lib.fio3_destroy.argtypes = [vp]
     lib.fio_select_q.argtypes = [i, ctypes.POINTER(_CPhase), ctypes.POINTER(_COpts), ctypes.c_double, i, i, i,
                                  ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_double),
@@ -463,7 +465,7 @@ class Plan3:
     """Three-dimensional butterfly plan (``fio3_plan``): N^3 targets and
     frequencies, q^3 Chebyshev grids, octrees.  kind: FOURIER (x . k) or
     SPHERES (eq:ex3); s, lm as for :class:`Plan`; dtype complex64 or
-    complex128.  Forward apply only, one right-hand side (N, N, N)."""
+    complex128.  Forward and adjoint applies of one right-hand side (N, N, N)."""
 
     def __init__(self, N: int, q: int, kind: int = SPHERES, s: int | None = None, lm: int | None = None,
                  dtype: torch.dtype = torch.complex64):
@@ -499,3 +501,15 @@ class Plan3:
         st = torch.cuda.current_stream(self.device).cuda_stream
         _check(load_library().fio3_apply(self._h, f.data_ptr(), u.data_ptr(), st), "fio3_apply")
         return u
+
+    def adjoint(self, u: torch.Tensor) -> torch.Tensor:
+        """f = B^H u for u of shape (N, N, N), u[i1, i2, i3] = u(i/N)."""
+        if not isinstance(u, torch.Tensor) or not u.is_cuda or u.dtype != self.dtype:
+            raise TypeError(f"u must be a {self.dtype} CUDA (HIP) tensor")
+        if tuple(u.shape) != (self.N,) * 3:
+            raise ValueError(f"u must have shape ({self.N}, {self.N}, {self.N})")
+        u = u.contiguous()
+        f = torch.empty_like(u)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().fio3_apply_adjoint(self._h, u.data_ptr(), f.data_ptr(), st), "fio3_apply_adjoint")
+        return f

@@ -179,6 +179,31 @@ int fio3_apply(fio3_plan_t plan, const void *f, void *u, void *stream) {
     return e == hipSuccess ? FIO_OK : set_hip_error(e, "three-dimensional launch");
 }
 
+int fio3_apply_adjoint(fio3_plan_t plan, const void *u, void *f, void *stream) {
+    clear_error();
+    if (!plan) return set_error(FIO_EINVAL, "plan is NULL");
+    if (!f || !u || f == u) return set_error(FIO_EINVAL, "u and f must be distinct non-NULL device pointers");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != plan->device) e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return set_hip_error(e, "device");
+    const Geom3 &g = plan->g;
+    hipStream_t st = (hipStream_t)stream;
+    void *a = plan->w0, *b = plan->w1;
+    e = launch_step3_adj(plan->dtype, 4, g, plan->tb, plan->src, g.L - g.s, u, a, st);
+    for (int l = g.L - g.s; e == hipSuccess && l > g.lm; --l) {
+        e = launch_step3_adj(plan->dtype, 3, g, plan->tb, plan->src, l, a, b, st);
+        std::swap(a, b);
+    }
+    if (e == hipSuccess) e = launch_step3_adj(plan->dtype, 2, g, plan->tb, plan->src, g.lm, nullptr, a, st);
+    for (int l = g.lm; e == hipSuccess && l > g.s; --l) {
+        e = launch_step3_adj(plan->dtype, 1, g, plan->tb, plan->src, l, a, b, st);
+        std::swap(a, b);
+    }
+    if (e == hipSuccess) e = launch_step3_adj(plan->dtype, 0, g, plan->tb, plan->src, g.s, a, f, st);
+    return e == hipSuccess ? FIO_OK : set_hip_error(e, "three-dimensional adjoint launch");
+}
+
 int fio3_destroy(fio3_plan_t plan) {
     clear_error();
     if (!plan) return FIO_OK;

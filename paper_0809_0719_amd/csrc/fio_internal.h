@@ -157,6 +157,11 @@ struct Src3 {
 // 3 x-level, 4 termination (out = u).
 hipError_t launch_step3(int dtype, int step, const Geom3 &g, const Tab3 &tb, const Src3 &src, int level,
                         const void *in, void *out, hipStream_t st);
+// The conjugate transposes: step 4 termination^H (in = u), 3 x-level^H
+// (outputs at `level` -> inputs at level - 1), 2 switch^H (in place on out),
+// 1 p-level^H (likewise), 0 initialisation^H (out = f).
+hipError_t launch_step3_adj(int dtype, int step, const Geom3 &g, const Tab3 &tb, const Src3 &src, int level,
+                            const void *in, void *out, hipStream_t st);
 
 // Host helpers shared by the host sources (defined in fio_plan.cpp): the
 // calling thread's error message, and the parts of a plan other host code

@@ -411,6 +411,383 @@ __global__ __launch_bounds__(NT) void k3_term(Geom3 g, Tab3 tb, const cpx<T> *__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint: the conjugate transpose of every step, in reverse order.
+// ---------------------------------------------------------------------------
+
+// termination^H: box A at level L-s, for every B (level s)
+//   delta_t = E(x^A_t, p0(B)) sum_x prod_d L_{t_d}(x_d) conj E(x, p0(B)) u(x).
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k3_term_adj(Geom3 g, Tab3 tb, const cpx<T> *__restrict__ u,
+                                                  cpx<T> *__restrict__ wout) {
+    constexpr int QQQ = Q * Q * Q;
+    constexpr int MP = (512 + NT - 1) / NT;
+    __shared__ cpx<T> U[512];
+    __shared__ cpx<T> P2[Q * 8 * 8], P1[Q * Q * 8];
+    __shared__ T Tm[8][Q];
+    const int tid = threadIdx.x;
+    const int lA = g.L - g.s, nA = 1 << lA, m = 1 << g.s, nB = 1 << g.s, nB3 = nB * nB * nB, m3 = m * m * m;
+    if (linear_block() >= (size_t)nA * nA * nA) return;  // past the boxes (uniform)
+    const int iA = (int)linear_block();
+    int a1, a2, a3;
+    decode3(iA, nA, a1, a2, a3);
+    const T *Tt = pick_T3<T>(tb);
+    for (int i = tid; i < m * Q; i += NT) (&Tm[0][0])[i] = Tt[i];
+    XP3 xg[MP];
+    cpx<T> uv[MP];
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        const int j = min(tid + k * NT, m3 - 1);
+        const int j1 = j / (m * m), j2 = (j / m) % m, j3 = j % m;
+        xg[k] = make_xp3(g, (double)(a1 * m + j1) / g.N, (double)(a2 * m + j2) / g.N, (double)(a3 * m + j3) / g.N);
+        uv[k] = u[((size_t)(a1 * m + j1) * g.N + (a2 * m + j2)) * g.N + (a3 * m + j3)];
+    }
+    for (int iB = 0; iB < nB3; ++iB) {
+        int b1, b2, b3;
+        decode3(iB, nB, b1, b2, b3);
+        const Dir3 d = dir3(box_centre(b2, g.s), box_centre(b3, g.s));
+        const double rho = g.rho_scale * box_centre(b1, g.s);
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < MP; ++k) {
+            const int j = tid + k * NT;
+            if (j < m3) U[j] = cmulc(uv[k], cis<T>(rho * g3(xg[k], d)));
+        }
+        lds_barrier();
+        for (int i = tid; i < Q * m * m; i += NT) {  // P2[t1][j2][j3] = sum_j1 T[j1][t1] U[j1][j2][j3]
+            const int j23 = i % (m * m), t1 = i / (m * m);
+            cpx<T> a = {(T)0, (T)0};
+            for (int j1 = 0; j1 < m; ++j1) crfma(a, Tm[j1][t1], U[j1 * m * m + j23]);
+            P2[i] = a;
+        }
+        lds_barrier();
+        for (int i = tid; i < Q * Q * m; i += NT) {  // P1[t1][t2][j3] = sum_j2 T[j2][t2] P2[t1][j2][j3]
+            const int j3 = i % m, t2 = (i / m) % Q, t1 = i / (Q * m);
+            cpx<T> a = {(T)0, (T)0};
+            for (int j2 = 0; j2 < m; ++j2) crfma(a, Tm[j2][t2], P2[(t1 * m + j2) * m + j3]);
+            P1[i] = a;
+        }
+        lds_barrier();
+        cpx<T> *dst = wout + ((size_t)iA * nB3 + iB) * QQQ;
+        for (int t = tid; t < QQQ; t += NT) {
+            const int t1 = t / (Q * Q), t2 = (t / Q) % Q, t3 = t % Q;
+            cpx<T> a = {(T)0, (T)0};
+            for (int j3 = 0; j3 < m; ++j3) crfma(a, Tm[j3][t3], P1[(t1 * Q + t2) * m + j3]);
+            const XP3 xt = make_xp3(g, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]),
+                                    box_node(a3, lA, tb.z[t3]));
+            dst[t] = cmul(a, cis<T>(rho * g3(xt, d)));
+        }
+    }
+}
+
+// x-level^H at level l: one workgroup per input pair (A_p at l-1, B_c at L-l+1),
+// gathering its eight children A (with B the parent of B_c):
+//   delta'_t' = E(x^{A_p}_t', p0(B_c)) sum_A sum_t prod_d L_{t'_d}(x^A_{t_d}) conj E(x^A_t, p0(B_c)) delta_t.
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k3_xlevel_adj(Geom3 g, Tab3 tb, int level, const cpx<T> *__restrict__ win,
+                                                    cpx<T> *__restrict__ wout) {
+    constexpr int QQQ = Q * Q * Q, TPT = (QQQ + NT - 1) / NT;
+    __shared__ cpx<T> V[QQQ], T1[QQQ], T2[QQQ];
+    __shared__ T Ms[2][Q][Q];
+    const int tid = threadIdx.x;
+    const int lB = g.L - level, nA = 1 << level, nB = 1 << lB, nB3 = nB * nB * nB;
+    const int nAp = nA / 2, nBc = 2 * nB, nBc3 = nBc * nBc * nBc;
+    if (linear_block() >= ((size_t)nAp * nAp * nAp) * nBc3) return;  // past the pairs (uniform)
+    const int pin = (int)linear_block(), iAp = pin / nBc3, iBc = pin - iAp * nBc3;
+    int ap1, ap2, ap3, bc1, bc2, bc3;
+    decode3(iAp, nAp, ap1, ap2, ap3);
+    decode3(iBc, nBc, bc1, bc2, bc3);
+    const int iB = ((bc1 >> 1) * nB + (bc2 >> 1)) * nB + (bc3 >> 1);
+    const T *Mg = pick_M3<T>(tb);
+    for (int i = tid; i < 2 * Q * Q; i += NT) (&Ms[0][0][0])[i] = Mg[i];
+    const Dir3 d = dir3(box_centre(bc2, lB + 1), box_centre(bc3, lB + 1));
+    const double rho = g.rho_scale * box_centre(bc1, lB + 1);
+    cpx<T> acc[TPT];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) acc[k] = {(T)0, (T)0};
+    for (int a = 0; a < 8; ++a) {
+        const int x1b = a >> 2, x2b = (a >> 1) & 1, x3b = a & 1;
+        const int a1 = 2 * ap1 + x1b, a2 = 2 * ap2 + x2b, a3 = 2 * ap3 + x3b;
+        const int iA = (a1 * nA + a2) * nA + a3;
+        const cpx<T> *src = win + ((size_t)iA * nB3 + iB) * QQQ;
+        lds_barrier();  // the previous child's readers are done
+        for (int t = tid; t < QQQ; t += NT) {
+            const int t1 = t / (Q * Q), t2 = (t / Q) % Q, t3 = t % Q;
+            const XP3 xt = make_xp3(g, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[t2]),
+                                    box_node(a3, level, tb.z[t3]));
+            V[t] = cmulc(src[t], cis<T>(rho * g3(xt, d)));
+        }
+        lds_barrier();
+        for (int i = tid; i < QQQ; i += NT) {  // T1[t1][t2][s3] = sum_t3 L_s3(x_t3) V[t1][t2][t3]
+            const int s3 = i % Q, t12 = i / Q;
+            cpx<T> v = {(T)0, (T)0};
+#pragma unroll
+            for (int t3 = 0; t3 < Q; ++t3) crfma(v, Ms[x3b][s3][t3], V[t12 * Q + t3]);
+            T1[i] = v;
+        }
+        lds_barrier();
+        for (int i = tid; i < QQQ; i += NT) {  // T2[t1][s2][s3] = sum_t2 L_s2(x_t2) T1[t1][t2][s3]
+            const int s3 = i % Q, s2 = (i / Q) % Q, t1 = i / (Q * Q);
+            cpx<T> v = {(T)0, (T)0};
+#pragma unroll
+            for (int t2 = 0; t2 < Q; ++t2) crfma(v, Ms[x2b][s2][t2], T1[(t1 * Q + t2) * Q + s3]);
+            T2[i] = v;
+        }
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const int s = tid + k * NT;
+            if (s < QQQ) {
+                const int s1 = s / (Q * Q), s23 = s % (Q * Q);
+                cpx<T> v = acc[k];
+#pragma unroll
+                for (int t1 = 0; t1 < Q; ++t1) crfma(v, Ms[x1b][s1][t1], T2[t1 * Q * Q + s23]);
+                acc[k] = v;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const int s = tid + k * NT;
+        if (s < QQQ) {
+            const int s1 = s / (Q * Q), s2 = (s / Q) % Q, s3 = s % Q;
+            const XP3 xp = make_xp3(g, box_node(ap1, level - 1, tb.z[s1]), box_node(ap2, level - 1, tb.z[s2]),
+                                    box_node(ap3, level - 1, tb.z[s3]));
+            wout[(size_t)pin * QQQ + s] = cmul(acc[k], cis<T>(rho * g3(xp, d)));
+        }
+    }
+}
+
+// switch^H, in place: delta_s <- sum_t conj E(x^A_t, p^B_s) delta_t.
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k3_switch_adj(Geom3 g, Tab3 tb, cpx<T> *__restrict__ w) {
+    constexpr int QQQ = Q * Q * Q, TPT = (QQQ + NT - 1) / NT;
+    __shared__ cpx<T> ds[QQQ];
+    __shared__ XP3 xs[QQQ];
+    const int tid = threadIdx.x;
+    const int lA = g.lm, lB = g.L - g.lm, nA = 1 << lA, nB = 1 << lB, nB3 = nB * nB * nB;
+    if (linear_block() >= ((size_t)nA * nA * nA) * nB3) return;  // past the pairs (uniform)
+    const int pair = (int)linear_block(), iA = pair / nB3, iB = pair - iA * nB3;
+    int a1, a2, a3, b1, b2, b3;
+    decode3(iA, nA, a1, a2, a3);
+    decode3(iB, nB, b1, b2, b3);
+    cpx<T> *wp = w + (size_t)pair * QQQ;
+    for (int t = tid; t < QQQ; t += NT) {
+        ds[t] = wp[t];
+        const int t1 = t / (Q * Q), t2 = (t / Q) % Q, t3 = t % Q;
+        xs[t] = make_xp3(g, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]), box_node(a3, lA, tb.z[t3]));
+    }
+    lds_barrier();
+    cpx<T> out[TPT];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const int s = tid + k * NT;
+        out[k] = {(T)0, (T)0};
+        if (s < QQQ) {
+            const int s1 = s / (Q * Q), s2 = (s / Q) % Q, s3 = s % Q;
+            const Dir3 d = dir3(box_node(b2, lB, tb.z[s2]), box_node(b3, lB, tb.z[s3]));
+            const double rho = g.rho_scale * box_node(b1, lB, tb.z[s1]);
+            cpx<T> a = {(T)0, (T)0};
+            for (int t = 0; t < QQQ; ++t) {
+                const cpx<T> e = cis<T>(rho * g3(xs[t], d));
+                cfma(a, cpx<T>{e.re, -e.im}, ds[t]);
+            }
+            out[k] = a;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const int s = tid + k * NT;
+        if (s < QQQ) wp[s] = out[k];  // every read of this pair happened before the barrier above
+    }
+}
+
+// p-level^H at level l: one workgroup per input pair (A_p at l-1, B_c at L-l+1),
+// B the parent of B_c (child index c), gathering the eight children A of A_p:
+//   delta'_t' = sum_A conj E(x0(A), p^{B_c}_t') sum_t prod_d M_{c_d}[t_d][t'_d] E(x0(A), p^B_t) delta_t.
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k3_plevel_adj(Geom3 g, Tab3 tb, int level, const cpx<T> *__restrict__ win,
+                                                    cpx<T> *__restrict__ wout) {
+    constexpr int QQQ = Q * Q * Q, TPT = (QQQ + NT - 1) / NT;
+    __shared__ cpx<T> V[QQQ], T1[QQQ], T2[QQQ];
+    __shared__ T Ms[2][Q][Q];
+    const int tid = threadIdx.x;
+    const int lB = g.L - level, nA = 1 << level, nB = 1 << lB, nB3 = nB * nB * nB;
+    const int nAp = nA / 2, nBc = 2 * nB, nBc3 = nBc * nBc * nBc;
+    if (linear_block() >= ((size_t)nAp * nAp * nAp) * nBc3) return;  // past the pairs (uniform)
+    const int pin = (int)linear_block(), iAp = pin / nBc3, iBc = pin - iAp * nBc3;
+    int ap1, ap2, ap3, bc1, bc2, bc3;
+    decode3(iAp, nAp, ap1, ap2, ap3);
+    decode3(iBc, nBc, bc1, bc2, bc3);
+    const int b1 = bc1 >> 1, b2 = bc2 >> 1, b3 = bc3 >> 1, c1 = bc1 & 1, c2 = bc2 & 1, c3 = bc3 & 1;
+    const int iB = (b1 * nB + b2) * nB + b3;
+    const T *Mg = pick_M3<T>(tb);
+    for (int i = tid; i < 2 * Q * Q; i += NT) (&Ms[0][0][0])[i] = Mg[i];
+    cpx<T> acc[TPT];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) acc[k] = {(T)0, (T)0};
+    for (int a = 0; a < 8; ++a) {
+        const int a1 = 2 * ap1 + (a >> 2), a2 = 2 * ap2 + ((a >> 1) & 1), a3 = 2 * ap3 + (a & 1);
+        const int iA = (a1 * nA + a2) * nA + a3;
+        const XP3 x0 = make_xp3(g, box_centre(a1, level), box_centre(a2, level), box_centre(a3, level));
+        const cpx<T> *src = win + ((size_t)iA * nB3 + iB) * QQQ;
+        lds_barrier();
+        for (int t = tid; t < QQQ; t += NT) {
+            const int t1 = t / (Q * Q), t2 = (t / Q) % Q, t3 = t % Q;
+            const Dir3 d = dir3(box_node(b2, lB, tb.z[t2]), box_node(b3, lB, tb.z[t3]));
+            V[t] = cmul(src[t], cis<T>(g.rho_scale * box_node(b1, lB, tb.z[t1]) * g3(x0, d)));
+        }
+        lds_barrier();
+        for (int i = tid; i < QQQ; i += NT) {  // T1[t1][t2][s3] = sum_t3 M_c3[t3][s3] V[t1][t2][t3]
+            const int s3 = i % Q, t12 = i / Q;
+            cpx<T> v = {(T)0, (T)0};
+#pragma unroll
+            for (int t3 = 0; t3 < Q; ++t3) crfma(v, Ms[c3][t3][s3], V[t12 * Q + t3]);
+            T1[i] = v;
+        }
+        lds_barrier();
+        for (int i = tid; i < QQQ; i += NT) {  // T2[t1][s2][s3] = sum_t2 M_c2[t2][s2] T1[t1][t2][s3]
+            const int s3 = i % Q, s2 = (i / Q) % Q, t1 = i / (Q * Q);
+            cpx<T> v = {(T)0, (T)0};
+#pragma unroll
+            for (int t2 = 0; t2 < Q; ++t2) crfma(v, Ms[c2][t2][s2], T1[(t1 * Q + t2) * Q + s3]);
+            T2[i] = v;
+        }
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const int s = tid + k * NT;
+            if (s < QQQ) {
+                const int s1 = s / (Q * Q), s2 = (s / Q) % Q, s3 = s % Q, s23 = s % (Q * Q);
+                cpx<T> v = {(T)0, (T)0};
+#pragma unroll
+                for (int t1 = 0; t1 < Q; ++t1) crfma(v, Ms[c1][t1][s1], T2[t1 * Q * Q + s23]);
+                const Dir3 d = dir3(box_node(bc2, lB + 1, tb.z[s2]), box_node(bc3, lB + 1, tb.z[s3]));
+                const double rho = g.rho_scale * box_node(bc1, lB + 1, tb.z[s1]);
+                cfma(acc[k], cmulc(v, cis<T>(rho * g3(x0, d))), cpx<T>{(T)1, (T)0});
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const int s = tid + k * NT;
+        if (s < QQQ) wout[(size_t)pin * QQQ + s] = acc[k];
+    }
+}
+
+// initialisation^H: one workgroup per box B (level L-s), its sources in chunks
+//   f(k) = sum_A conj E(x0(A), k) sum_t L^B_t(p_k) E(x0(A), p^B_t) delta^{AB}_t.
+template <typename T, int Q>
+__global__ __launch_bounds__(NT) void k3_init_adj(Geom3 g, Tab3 tb, Src3 src, const cpx<T> *__restrict__ w,
+                                                  cpx<T> *__restrict__ f) {
+    constexpr int QQQ = Q * Q * Q;
+    __shared__ cpx<T> y[QQQ];
+    __shared__ T lg[3][C3][Q];
+    const int tid = threadIdx.x;
+    const int lB = g.L - g.s, nA = 1 << g.s, nA3 = nA * nA * nA, nB = 1 << lB, nB3 = nB * nB * nB;
+    if (linear_block() >= (size_t)nB3) return;  // past the boxes (uniform)
+    const int iB = (int)linear_block();
+    int b1, b2, b3;
+    decode3(iB, nB, b1, b2, b3);
+    const int beg = src.off[iB], np = src.off[iB + 1] - beg;
+    const int N = g.N, h = N / 2;
+    for (int j0 = 0; j0 < np; j0 += C3) {
+        const int nc = min(C3, np - j0);
+        int kk = 0;
+        double k1 = 0, k2 = 0, k3 = 0;
+        lds_barrier();
+        if (tid < nc) {
+            const int j = beg + j0 + tid;
+            kk = src.idx[j];
+            k1 = (double)(kk / (N * N) - h);
+            k2 = (double)((kk / N) % N - h);
+            k3 = (double)(kk % N - h);
+            const int bb[3] = {b1, b2, b3};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double u = (src.p[3 * j + d] - box_centre(bb[d], lB)) * nB;
+#pragma unroll
+                for (int t = 0; t < Q; ++t) {
+                    double v = tb.lam[t];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i)
+                        if (i != t) v *= u - tb.z[i];
+                    lg[d][tid][t] = (T)v;
+                }
+            }
+        }
+        cpx<T> acc = {(T)0, (T)0};
+        for (int iA = 0; iA < nA3; ++iA) {
+            int a1, a2, a3;
+            decode3(iA, nA, a1, a2, a3);
+            const XP3 x0 = make_xp3(g, box_centre(a1, g.s), box_centre(a2, g.s), box_centre(a3, g.s));
+            lds_barrier();  // lg written (first A) / the previous A's readers of y are done
+            const cpx<T> *sw = w + ((size_t)iA * nB3 + iB) * QQQ;
+            for (int t = tid; t < QQQ; t += NT) {
+                const int t1 = t / (Q * Q), t2 = (t / Q) % Q, t3 = t % Q;
+                const Dir3 d = dir3(box_node(b2, lB, tb.z[t2]), box_node(b3, lB, tb.z[t3]));
+                y[t] = cmul(sw[t], cis<T>(g.rho_scale * box_node(b1, lB, tb.z[t1]) * g3(x0, d)));
+            }
+            lds_barrier();
+            if (tid < nc) {
+                cpx<T> v = {(T)0, (T)0};
+                for (int t1 = 0; t1 < Q; ++t1)
+                    for (int t2 = 0; t2 < Q; ++t2) {
+                        const T l12 = lg[0][tid][t1] * lg[1][tid][t2];
+#pragma unroll
+                        for (int t3 = 0; t3 < Q; ++t3) crfma(v, l12 * lg[2][tid][t3], y[(t1 * Q + t2) * Q + t3]);
+                    }
+                cfma(acc, cmulc(v, cis<T>(phase3_cart(x0, k1, k2, k3))), cpx<T>{(T)1, (T)0});
+            }
+        }
+        if (tid < nc) f[kk] = acc;
+    }
+}
+
+template <typename T>
+static hipError_t step3_adj_t(int step, const Geom3 &g, const Tab3 &tb, const Src3 &src, int level, const void *in,
+                              void *out, hipStream_t st) {
+    const size_t pairs = (size_t)1 << (3 * g.L);
+#define L3A(Q)                                                                                                    \
+    switch (step) {                                                                                               \
+        case 0:                                                                                                   \
+            hipLaunchKernelGGL((k3_init_adj<T, Q>), grid_of((size_t)1 << (3 * (g.L - g.s))), dim3(NT), 0, st, g, \
+                               tb, src, (const cpx<T> *)in, (cpx<T> *)out);                                      \
+            break;                                                                                                \
+        case 1:                                                                                                   \
+            hipLaunchKernelGGL((k3_plevel_adj<T, Q>), grid_of(pairs), dim3(NT), 0, st, g, tb, level,             \
+                               (const cpx<T> *)in, (cpx<T> *)out);                                                \
+            break;                                                                                                \
+        case 2:                                                                                                   \
+            hipLaunchKernelGGL((k3_switch_adj<T, Q>), grid_of(pairs), dim3(NT), 0, st, g, tb, (cpx<T> *)out);    \
+            break;                                                                                                \
+        case 3:                                                                                                   \
+            hipLaunchKernelGGL((k3_xlevel_adj<T, Q>), grid_of(pairs), dim3(NT), 0, st, g, tb, level,             \
+                               (const cpx<T> *)in, (cpx<T> *)out);                                                \
+            break;                                                                                                \
+        default:                                                                                                  \
+            hipLaunchKernelGGL((k3_term_adj<T, Q>), grid_of((size_t)1 << (3 * (g.L - g.s))), dim3(NT), 0, st,    \
+                               g, tb, (const cpx<T> *)in, (cpx<T> *)out);                                         \
+    }
+    switch (g.q) {
+        case 3: L3A(3) break;
+        case 4: L3A(4) break;
+        case 5: L3A(5) break;
+        case 6: L3A(6) break;
+        case 7: L3A(7) break;
+        case 8: L3A(8) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef L3A
+    return hipGetLastError();
+}
+
+hipError_t launch_step3_adj(int dtype, int step, const Geom3 &g, const Tab3 &tb, const Src3 &src, int level,
+                            const void *in, void *out, hipStream_t st) {
+    return dtype == FIO_C128 ? step3_adj_t<double>(step, g, tb, src, level, in, out, st)
+                             : step3_adj_t<float>(step, g, tb, src, level, in, out, st);
+}
+
 template <typename T>
 static hipError_t step3_t(int step, const Geom3 &g, const Tab3 &tb, const Src3 &src, int level, const void *in,
                           void *out, hipStream_t st) {

@@ -93,3 +93,43 @@ def test_3d_bad_arguments():
     assert lib.fio3_apply(plan._h, f.data_ptr(), f.data_ptr(), None) == -1   # u aliases f
     with pytest.raises(ValueError):
         plan.apply(torch.zeros((8, 8, 4), dtype=torch.complex64, device="cuda"))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 2e-5)])
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_3d_adjoint_identity(case, dtype, tol):
+    """<v, B f> = <B^H v, f> with the forward that the oracle pins above: the
+    adjoint is the exact conjugate transpose of every step."""
+    import paper_0809_0719_amd as fio
+    N, q, kind, s, lm = case
+    plan = fio.Plan3(N, q, kind, s=s, lm=lm, dtype=dtype)
+    f = torch.as_tensor(_noise(N, 11)).to(dtype).cuda()
+    v = torch.as_tensor(_noise(N, 12)).to(dtype).cuda()
+    u = plan.apply(f)
+    g = plan.adjoint(v)
+    lhs = torch.vdot(v.flatten().to(torch.complex128), u.flatten().to(torch.complex128)).item()
+    rhs = torch.vdot(g.flatten().to(torch.complex128), f.flatten().to(torch.complex128)).item()
+    print(f"3-D adjoint {case} {dtype}: <v,Bf> {lhs:.6e} <B^H v,f> {rhs:.6e}")
+    assert abs(lhs - rhs) <= tol * abs(lhs)
+
+
+def test_3d_adjoint_is_the_oracle_transpose():
+    """N = 4, q = 5, eq:ex3, FP64: the dense matrix of the oracle's 3-D
+    butterfly (its applies to the 64 unit inputs) transposed and conjugated,
+    applied to v, against the library's adjoint."""
+    import paper_0809_0719_amd as fio
+    N, q = 4, 5
+    model = B.ButterflyModel3(N, q, B.SPHERES)
+    n3 = N ** 3
+    Bm = np.empty((n3, n3), dtype=np.complex128)
+    for j in range(n3):
+        e = np.zeros(n3, dtype=np.complex128)
+        e[j] = 1.0
+        Bm[:, j] = model.apply(e.reshape(N, N, N)).ravel()
+    v = _noise(N, 13)
+    ref = (Bm.conj().T @ v.ravel()).reshape(N, N, N)
+    plan = fio.Plan3(N, q, fio.SPHERES, dtype=torch.complex128)
+    got = plan.adjoint(torch.as_tensor(v).cuda()).cpu().numpy()
+    e = rel_max(got, ref)
+    print(f"3-D adjoint vs dense oracle transpose: {e:.2e}")
+    assert e <= 1e-12
