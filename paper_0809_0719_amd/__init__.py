@@ -25,7 +25,8 @@ from dataclasses import dataclass
 import torch
 
 __all__ = [
-    "Phase", "Plan", "Plan3", "Batch", "FIOApply", "FIOApplyPhase", "fio_apply", "direct_rows", "select_q",
+    "Phase", "Plan", "Plan3", "Batch", "FIOApply", "FIOApply3", "FIOApplyPhase", "fio_apply", "direct_rows",
+    "select_q",
     "load_library", "library_path",
     "FOURIER", "ELLIPSE", "C128", "C64", "EXPORTED_SYMBOLS",
 ]
@@ -513,3 +514,16 @@ class Plan3:
         st = torch.cuda.current_stream(self.device).cuda_stream
         _check(load_library().fio3_apply_adjoint(self._h, u.data_ptr(), f.data_ptr(), st), "fio3_apply_adjoint")
         return f
+
+
+class FIOApply3(torch.autograd.Function):
+    """u = B f for a :class:`Plan3`, with backward grad_f = B^H grad_u."""
+
+    @staticmethod
+    def forward(ctx, f: torch.Tensor, plan: Plan3):
+        ctx.plan = plan
+        return plan.apply(f)
+
+    @staticmethod
+    def backward(ctx, grad_u: torch.Tensor):
+        return ctx.plan.adjoint(grad_u.contiguous()), None

@@ -133,3 +133,18 @@ def test_3d_adjoint_is_the_oracle_transpose():
     e = rel_max(got, ref)
     print(f"3-D adjoint vs dense oracle transpose: {e:.2e}")
     assert e <= 1e-12
+
+
+def test_3d_autograd_backward_is_the_adjoint():
+    """L = ||B f - y||^2 through FIOApply3: dL/d conj(f) = B^H (B f - y), the
+    conjugate-Wirtinger gradient torch uses, equals 2 B^H(Bf - y) in torch's
+    convention for real losses."""
+    import paper_0809_0719_amd as fio
+    N, q = 8, 5
+    plan = fio.Plan3(N, q, fio.SPHERES, dtype=torch.complex128)
+    f = torch.as_tensor(_noise(N, 14)).cuda().requires_grad_(True)
+    y = torch.as_tensor(_noise(N, 15)).cuda()
+    loss = (fio.FIOApply3.apply(f, plan) - y).abs().pow(2).sum()
+    loss.backward()
+    ref = 2 * plan.adjoint(plan.apply(f.detach()) - y)
+    assert rel_l2(f.grad.cpu().numpy(), ref.cpu().numpy()) <= 1e-12
