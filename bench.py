@@ -167,6 +167,52 @@ def bench_3d(N: int, q: int, steps: int, warmup: int, rows: int):
                       "config": {"workload": f"eq:ex3 3-D N={N} q={q}", "N": N, "q": q}}), flush=True)
 
 
+def bench_mixed(steps: int, warmup: int, nstreams: int):
+    """The uneven batch: 32 problems drawn by the mixed-batch recipe (N in
+    {128, 256, 512, 1024}, a tolerance in {1e-2, 1e-4, 1e-6} mapped to q =
+    5 / 7 / 9, eta ~ U[0, 0.3]^2), one right-hand side each, through a Batch
+    (internal streams) and, for comparison, one plan after another on one
+    stream.  value = problems per second through the batch."""
+    import torch
+
+    import paper_0809_0719_amd as fio
+    from workloads import mixed_batch, white_noise
+
+    torch.cuda.set_device(0)
+    qmap = {1e-2: 5, 1e-4: 7, 1e-6: 9}
+    probs = mixed_batch(6, n=32)
+    plans, fs = [], []
+    for p in probs:
+        plans.append(fio.Plan(p["N"], qmap[p["tol"]], fio.Phase(eta1=p["eta1"], eta2=p["eta2"])))
+        fs.append(torch.as_tensor(white_noise(p["N"], p["f_seed"] % 100000)).to(torch.complex64).cuda())
+    batch = fio.Batch(plans, nstreams=nstreams)
+    outs = [torch.empty_like(f) for f in fs]
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t_batch = timed(lambda: batch.apply(fs, outs))
+    t_serial = timed(lambda: [p.apply(f, out=o) for p, f, o in zip(plans, fs, outs)])
+    counts = {}
+    for p in probs:
+        key = f"N{p['N']}-q{qmap[p['tol']]}"
+        counts[key] = counts.get(key, 0) + 1
+    print(json.dumps({"metric": "mixed-batch FIO applies/sec", "value": len(plans) / t_batch, "unit": "applies/s",
+                      "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": t_batch * 1e3,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+                      "data": "synthetic", "serial_ms_per_step": t_serial * 1e3,
+                      "speedup_vs_serial": t_serial / t_batch,
+                      "config": {"workload": "32 problems, eq:ex1 with eta ~ U[0,0.3]^2", "nstreams": nstreams,
+                                 "problems": counts}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +229,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dims", type=int, choices=[2, 3], default=2,
                     help="3: the three-dimensional example eq:ex3 (forward applies, --N3, --q3)")
+    ap.add_argument("--mixed", action="store_true",
+                    help="the uneven batch of 32 problems through a Batch, against one plan after another")
+    ap.add_argument("--nstreams", type=int, default=4)
     ap.add_argument("--N3", type=int, default=64)
     ap.add_argument("--q3", type=int, default=7)
     ap.add_argument("--copy-calib", action="store_true",
@@ -190,6 +239,9 @@ def main():
     args = ap.parse_args()
     if args.copy_calib:
         copy_calibration()
+        return
+    if args.mixed:
+        bench_mixed(args.steps, args.warmup, args.nstreams)
         return
     if args.dims == 3:
         bench_3d(args.N3, args.q3, args.steps, args.warmup, 64 if args.N3 <= 128 else 16)
