@@ -29,6 +29,8 @@
 // B operand B[l/16][l%16], accumulator element v of lane l is D[4(l/16)+v][l%16].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fio_kernels_common.h"
 
 namespace fio {
@@ -38,6 +40,21 @@ using f32x4 = __attribute__((ext_vector_type(4))) float;
 constexpr int IM_NA = 64;  // A boxes at level 3
 
 bool init_mfma_supported(int q, int s) { return s == 3 && q >= QMIN && q <= 9; }
+
+// Workgroups per box: the right-hand sides of a box are split into up to
+// IM_CH chunks of passes, one workgroup each.  Workgroup w runs on XCD
+// w mod 8 (round-robin dispatch); numbering boxes so that the chunks of one
+// box are the workgroups k*8 + x, ..., (k + IM_CH - 1)*8 + x of one XCD x
+// puts them on that XCD at about the same time, so the box's rows of the K
+// and E tables are fetched from HBM once and then served by that XCD's L2
+// (with every chunk of every box in flight at once, the tables of the boxes
+// active on an XCD exceed its L2 and are re-read from HBM per pass).
+constexpr int IM_CH = 8;
+__device__ __forceinline__ void im_box_chunk(int nch, uint32_t &box, int &chunk) {
+    const uint32_t w = blockIdx.x, x = w & 7u, k = w >> 3;
+    box = (k / (uint32_t)nch) * 8u + x;
+    chunk = (int)(k % (uint32_t)nch);
+}
 
 // Row length of the K table: q^2 padded to the forward kernel's row tiles.
 constexpr int im_ks(int q) { return (q * q + 15) / 16 * 16; }
@@ -133,7 +150,7 @@ template <int Q, int RCI>
 __global__ __launch_bounds__(NT, 2) void k_init_mm(Geom g, PhaseDev ph, Tables tb, Sources src,
                                                    const float *__restrict__ Kt, const cpx<float> *__restrict__ Et,
                                                    const cpx<float> *__restrict__ fsrt, cpx<float> *__restrict__ w,
-                                                   int nrhs, size_t plane) {
+                                                   int nrhs, size_t plane, int nch, int ppc) {
     constexpr int QQ = Q * Q;
     constexpr int TT = (QQ + 15) / 16;  // row tiles of t
     constexpr int KS = im_ks(Q);
@@ -145,7 +162,9 @@ __global__ __launch_bounds__(NT, 2) void k_init_mm(Geom g, PhaseDev ph, Tables t
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int cl = lane & 15, kq = lane >> 4;
-    const uint32_t mB = blockIdx.x;
+    uint32_t mB;
+    int chunk;
+    im_box_chunk(nch, mB, chunk);  // passes [chunk ppc, (chunk + 1) ppc) of box mB
     int bp1, bp2;
     morton_decode(mB, bp1, bp2);
     const int n2 = g.N * g.N;
@@ -159,7 +178,8 @@ __global__ __launch_bounds__(NT, 2) void k_init_mm(Geom g, PhaseDev ph, Tables t
 #pragma unroll
     for (int ct = 0; ct < CTW; ++ct) acol[ct] = ((((wv * CTW + ct) * 16 + cl) >> 1)) & (IM_NA - 1);
 
-    for (int r0 = 0; r0 < nrhs; r0 += RCI) {
+    const int rend = min(nrhs, (chunk + 1) * ppc * RCI);
+    for (int r0 = chunk * ppc * RCI; r0 < rend; r0 += RCI) {
         const int r = r0 + rl;
         const bool rok = r < nrhs;
         const cpx<float> *fr = fsrt + (size_t)min(r, nrhs - 1) * n2 + beg;
@@ -233,7 +253,8 @@ __global__ __launch_bounds__(NT, 2) void k_init_adj_mm(Geom g, PhaseDev ph, Tabl
                                                        const float *__restrict__ Kt,
                                                        const cpx<float> *__restrict__ Et,
                                                        const cpx<float> *__restrict__ win,
-                                                       cpx<float> *__restrict__ f, int nrhs, size_t plane) {
+                                                       cpx<float> *__restrict__ f, int nrhs, size_t plane, int nch,
+                                                       int ppc) {
     constexpr int QQ = Q * Q;
     constexpr int KT = (QQ + 3) / 4;   // reduction steps over t (t = 4 ks + lane / 16)
     constexpr int KS = im_ks(Q);
@@ -250,7 +271,9 @@ __global__ __launch_bounds__(NT, 2) void k_init_adj_mm(Geom g, PhaseDev ph, Tabl
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int cl = lane & 15, kq = lane >> 4;
-    const uint32_t mB = blockIdx.x;
+    uint32_t mB;
+    int chunk;
+    im_box_chunk(nch, mB, chunk);  // right-hand sides [chunk ppc, (chunk + 1) ppc) of box mB
     int bp1, bp2;
     morton_decode(mB, bp1, bp2);
     const int n2 = g.N * g.N;
@@ -307,7 +330,8 @@ __global__ __launch_bounds__(NT, 2) void k_init_adj_mm(Geom g, PhaseDev ph, Tabl
     int arow[CTW];
 #pragma unroll
     for (int ct = 0; ct < CTW; ++ct) arow[ct] = (((wv * CTW + ct) * 16 + cl) >> 1) & (IM_NA - 1);
-    for (int r = 0; r < nrhs; ++r) {
+    const int rend = min(nrhs, (chunk + 1) * ppc);
+    for (int r = chunk * ppc; r < rend; ++r) {
         float wa[CTW][KT];
 #pragma unroll
         for (int ct = 0; ct < CTW; ++ct) {
@@ -410,16 +434,19 @@ hipError_t launch_init_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb,
     const int n2 = g.N * g.N;
     hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)(((size_t)n2 * nrhs + NT - 1) / NT)), dim3(NT), 0, st,
                        (const cpx<float> *)f, src.idx, (cpx<float> *)fsorted, n2, nrhs);
-    const unsigned nB = 1u << (2 * (g.L - g.s));
+    const unsigned nB = 1u << (2 * (g.L - g.s));  // a multiple of 8 (s = 3, N >= 64)
+    if (nB % 8) return hipErrorInvalidValue;
+    const int rci = nrhs == 1 ? 1 : 2, npass = (nrhs + rci - 1) / rci;
+    const int nch = std::min(IM_CH, npass), ppc = (npass + nch - 1) / nch;
 #define L_IMM(Q)                                                                                          \
     if (nrhs == 1)                                                                                        \
-        hipLaunchKernelGGL((k_init_mm<Q, 1>), dim3(nB), dim3(NT), 0, st, g, ph, tb, src,                  \
+        hipLaunchKernelGGL((k_init_mm<Q, 1>), dim3(nB * nch), dim3(NT), 0, st, g, ph, tb, src,            \
                            (const float *)ktab, (const cpx<float> *)etab, (const cpx<float> *)fsorted,    \
-                           (cpx<float> *)w, nrhs, plane);                                                 \
+                           (cpx<float> *)w, nrhs, plane, nch, ppc);                                       \
     else                                                                                                  \
-        hipLaunchKernelGGL((k_init_mm<Q, 2>), dim3(nB), dim3(NT), 0, st, g, ph, tb, src,                  \
+        hipLaunchKernelGGL((k_init_mm<Q, 2>), dim3(nB * nch), dim3(NT), 0, st, g, ph, tb, src,            \
                            (const float *)ktab, (const cpx<float> *)etab, (const cpx<float> *)fsorted,    \
-                           (cpx<float> *)w, nrhs, plane);
+                           (cpx<float> *)w, nrhs, plane, nch, ppc);
     FIO_DISPATCH_QI(g.q, L_IMM)
 #undef L_IMM
     return hipGetLastError();
@@ -429,10 +456,13 @@ hipError_t launch_init_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables 
                                 const void *ktab, const void *etab, const void *w, void *f, int nrhs,
                                 size_t plane, hipStream_t st) {
     if (!init_mfma_supported(g.q, g.s)) return hipErrorInvalidValue;
-    const unsigned nB = 1u << (2 * (g.L - g.s));
+    const unsigned nB = 1u << (2 * (g.L - g.s));  // a multiple of 8 (s = 3, N >= 64)
+    if (nB % 8) return hipErrorInvalidValue;
+    const int nch = std::min(IM_CH, nrhs), ppc = (nrhs + nch - 1) / nch;
 #define L_IAMM(Q)                                                                                         \
-    hipLaunchKernelGGL((k_init_adj_mm<Q>), dim3(nB), dim3(NT), 0, st, g, ph, tb, src, (const float *)ktab, \
-                       (const cpx<float> *)etab, (const cpx<float> *)w, (cpx<float> *)f, nrhs, plane);
+    hipLaunchKernelGGL((k_init_adj_mm<Q>), dim3(nB * nch), dim3(NT), 0, st, g, ph, tb, src,               \
+                       (const float *)ktab, (const cpx<float> *)etab, (const cpx<float> *)w, (cpx<float> *)f, \
+                       nrhs, plane, nch, ppc);
     FIO_DISPATCH_QI(g.q, L_IAMM)
 #undef L_IAMM
     return hipGetLastError();
