@@ -280,8 +280,14 @@ __global__ __launch_bounds__(NT) void k_switch(Geom g, PhaseDev ph, Tables tb, c
     constexpr int H = Q / 2;
     constexpr int HH = H > 0 ? H : 1;
     constexpr int PPB = NT / QQ;  // pairs per workgroup
-    __shared__ cpx<T> Sx[PPB][RC][Q][HH];
-    __shared__ cpx<T> Dx[PPB][RC][Q][HH];
+    // pair sums S and differences D, [rc][s2][j] per pair, the pair's block
+    // padded by two values: unpadded, the block (RC q floor(q/2) values) is a
+    // multiple of the 32 LDS banks at q = 9, and a wave that straddles two
+    // pairs reads both pairs' values from one bank; two values (16 bytes) keep
+    // the 16-byte alignment that lets S_j, S_j+1 load as one 128-bit read
+    constexpr int SDB = RC * Q * HH + 2;
+    __shared__ cpx<T> Sx[PPB][SDB];
+    __shared__ cpx<T> Dx[PPB][SDB];
     __shared__ cpx<T> Mid[PPB][RC][Q];
     __shared__ double cth[PPB][Q], sth[PPB][Q];
     __shared__ double rho0[PPB], hz[PPB][HH];
@@ -324,8 +330,8 @@ __global__ __launch_bounds__(NT) void k_switch(Geom g, PhaseDev ph, Tables tb, c
                 const cpx<T> *wp = w + (size_t)(r0 + rc) * plane + pair * QQ;
                 if (t1 < H) {
                     const cpx<T> a = wp[t1 * Q + t2], b = wp[(Q - 1 - t1) * Q + t2];
-                    Sx[pl][rc][t2][t1] = {a.re + b.re, a.im + b.im};
-                    Dx[pl][rc][t2][t1] = {a.re - b.re, a.im - b.im};
+                    Sx[pl][(rc * Q + t2) * HH + t1] = {a.re + b.re, a.im + b.im};
+                    Dx[pl][(rc * Q + t2) * HH + t1] = {a.re - b.re, a.im - b.im};
                 } else if ((Q & 1) && t1 == H) {
                     Mid[pl][rc][t2] = wp[H * Q + t2];
                 }
@@ -349,7 +355,7 @@ __global__ __launch_bounds__(NT) void k_switch(Geom g, PhaseDev ph, Tables tb, c
                     cpx<T> inner = (Q & 1) ? Mid[pl][rc][s2] : cpx<T>{(T)0, (T)0};
 #pragma unroll
                     for (int j = 0; j < H; ++j) {
-                        const cpx<T> S = Sx[pl][rc][s2][j], D = Dx[pl][rc][s2][j];
+                        const cpx<T> S = Sx[pl][(rc * Q + s2) * HH + j], D = Dx[pl][(rc * Q + s2) * HH + j];
                         inner.re = fma(d[j].re, S.re, fma(-d[j].im, D.im, inner.re));
                         inner.im = fma(d[j].re, S.im, fma(d[j].im, D.re, inner.im));
                     }

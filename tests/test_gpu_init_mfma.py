@@ -64,8 +64,12 @@ def test_mfma_initialisation_whole_pass_both_directions(N, q):
     assert eu <= FP32_TOL and ef <= FP32_TOL
 
 
-@pytest.mark.parametrize("nrhs", [2, 3, 5])
+@pytest.mark.parametrize("nrhs", [2, 3, 5, 17])
 def test_mfma_initialisation_batched_equals_one_by_one(nrhs):
+    """A box's right-hand sides are split over up to eight workgroups: 17 gives
+    the forward nine passes of two (chunks of two passes, the last chunks
+    empty) and the adjoint chunks of three right-hand sides (the last two
+    empty)."""
     N, q, ph = 64, 9, D.Phase()
     plan = _plan(N, q, ph, nrhs_max=nrhs)
     single = _plan(N, q, ph)
