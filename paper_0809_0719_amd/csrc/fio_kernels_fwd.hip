@@ -217,10 +217,7 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
     for (int r = 0; r < (HOIST ? nrhs : 1); ++r) {
         if (active) {
             if (!PF) load_row(r);
-            cpx<T> in[2 * Q];
-#pragma unroll
-            for (int k = 0; k < 2 * Q; ++k) in[k] = nx[k];
-            if (PF && r + 1 < nrhs) load_row(r + 1);
+            const cpx<T>(&in)[2 * Q] = nx;
             // first pass: row (c1, t'1)
             cpx<T> acc[Q];
 #pragma unroll
@@ -241,6 +238,9 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
             for (int tt = 0; tt < Q; ++tt) W[bbl][j][rr * Q + tt] = acc[tt];
         }
         lds_barrier();
+        // the next right-hand side's row is loaded during the second pass, once
+        // the first pass has consumed this one
+        if (PF && active && r + 1 < nrhs) load_row(r + 1);
         if (active) {
             // second pass: column t2, rows t1 of one half, then remodulation
             cpx<T> col[2 * Q];
