@@ -213,6 +213,74 @@ def bench_mixed(steps: int, warmup: int, nstreams: int):
                                  "problems": counts}}), flush=True)
 
 
+def bench_feature(kind: str, N: int, q: int, rank: int, steps: int, warmup: int):
+    """One of the extensions at the benchmark's (N, q), timed beside the plain
+    butterfly on the same plan:
+    * dphase: u and its derivatives du/da1, du/da2 with respect to the ellipse
+      scalings of one right-hand side (fio_apply_dphase, which takes the
+      right-hand sides one at a time); value = such triples per second,
+      against the plain single-right-hand-side forward;
+    * amplitude: a separated amplitude a(x,k) = sum_t g_t(x) h_t(k) of the
+      given rank, forward and adjoint (fio_apply_amplitude[_adjoint]); value
+      = amplitude applies per second (a forward and an adjoint count two),
+      against the rank right-hand sides of one batched forward and adjoint."""
+    import torch
+
+    import paper_0809_0719_amd as fio
+    from workloads import amplitude_factors, white_noise
+
+    torch.cuda.set_device(0)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    c64 = torch.complex64
+    if kind == "dphase":
+        plan = fio.Plan(N, q, fio.Phase(), dtype=c64)
+        f = torch.as_tensor(white_noise(N, 3)).to(c64).cuda()
+        u = torch.empty_like(f)
+        t_feat = timed(lambda: plan.apply_dphase(f))
+        t_plain = timed(lambda: plan.apply(f, out=u))
+        value = 1 / t_feat
+        metric, cfg = "FIO + phase-derivative applies/sec", {"nrhs": 1}
+    else:
+        plan = fio.Plan(N, q, fio.Phase(), dtype=c64, nrhs_max=rank)
+        g_h, h_h = amplitude_factors(N, rank, 7)
+        g, h = (torch.as_tensor(x).to(c64).cuda() for x in (g_h, h_h))
+        f = torch.as_tensor(white_noise(N, 3)).to(c64).cuda()
+        u = torch.empty_like(f)
+        b = torch.empty_like(f)
+        fr = torch.as_tensor(white_noise(N, 3, nrhs=rank)).to(c64).cuda()
+        ur = torch.empty_like(fr)
+        br = torch.empty_like(fr)
+
+        def amp():
+            plan.apply_amplitude(f, g, h, out=u)
+            plan.adjoint_amplitude(u, g, h, out=b)
+
+        def plain():
+            plan.apply(fr, out=ur)
+            plan.adjoint(ur, out=br)
+
+        t_feat = timed(amp)
+        t_plain = timed(plain)
+        value = 2 / t_feat
+        metric, cfg = "variable-amplitude FIO applies/sec", {"rank": rank}
+    print(json.dumps({"metric": metric, "value": value, "unit": "applies/s", "n_gpus": 1, "steps": steps,
+                      "warmup": warmup, "ms_per_step": t_feat * 1e3, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "plain_ms_per_step": t_plain * 1e3, "cost_vs_plain": t_feat / t_plain,
+                      "config": dict({"workload": f"eq:ex1 FIO butterfly N={N} q={q}, {kind}"}, **cfg)}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,9 +302,16 @@ def main():
     ap.add_argument("--nstreams", type=int, default=4)
     ap.add_argument("--N3", type=int, default=64)
     ap.add_argument("--q3", type=int, default=7)
+    ap.add_argument("--feature", choices=["dphase", "amplitude"],
+                    help="time an extension at (--N, --q) beside the plain butterfly on the same plan")
+    ap.add_argument("--rank", type=int, default=8, help="terms of the separated amplitude (--feature amplitude)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling the HBM byte counters)")
     args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the butterfly pass here is a single-GPU build "
+              "(--gpus 1).", file=sys.stderr)
+        sys.exit(2)
     if args.copy_calib:
         copy_calibration()
         return
@@ -246,11 +321,9 @@ def main():
     if args.dims == 3:
         bench_3d(args.N3, args.q3, args.steps, args.warmup, 64 if args.N3 <= 128 else 16)
         return
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the butterfly pass here is a single-GPU build "
-              "(--gpus 1).", file=sys.stderr)
-        sys.exit(2)
+    if args.feature:
+        bench_feature(args.feature, args.N, args.q, args.rank, args.steps, args.warmup)
+        return
 
     import torch
 

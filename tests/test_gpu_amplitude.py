@@ -11,7 +11,7 @@ import torch
 from oracle import amplitude as A
 from oracle import direct as D
 from oracle.butterfly import ButterflyModel
-from workloads import white_noise
+from workloads import amplitude_factors, white_noise
 
 from gpu_helpers import rel_l2, rel_max
 
@@ -23,17 +23,7 @@ FP32_TOL = 2e-5
 
 def _factors(N, rank, seed):
     """Smooth complex factors on the x grid (g) and the frequency grid (h)."""
-    rng = np.random.default_rng(seed)
-    i = np.arange(N)
-    x1, x2 = np.meshgrid(i / N, i / N, indexing="ij")
-    k1, k2 = np.meshgrid(i - N // 2, i - N // 2, indexing="ij")
-    g = np.empty((rank, N, N), complex)
-    h = np.empty((rank, N, N), complex)
-    for t in range(rank):
-        c = rng.standard_normal(6)
-        g[t] = (1 + 0.5 * c[0] * x1 + c[1] * x2 ** 2) * np.exp(1j * (c[2] * x1 - x2))
-        h[t] = 1 / (1 + 0.1 * (c[3] * k1 / N) ** 2 + (k2 / N + c[4]) ** 2) * np.exp(1j * c[5] * k1 / N)
-    return g, h
+    return amplitude_factors(N, rank, seed)
 
 
 def _dev(x, dtype):

@@ -46,6 +46,23 @@ def modulation_amplitudes(seed: int, n: int = 1) -> np.ndarray:
     return rng.uniform(0.0, 0.3, size=(n, 2))
 
 
+def amplitude_factors(N: int, rank: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Smooth complex factors of a separated amplitude a(x,k) = sum_t g_t(x)
+    h_t(k): g (rank, N, N) on the x grid x = i/N, h (rank, N, N) on the
+    frequency grid k = i - N/2; six N(0,1) coefficients per term."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(N)
+    x1, x2 = np.meshgrid(i / N, i / N, indexing="ij")
+    k1, k2 = np.meshgrid(i - N // 2, i - N // 2, indexing="ij")
+    g = np.empty((rank, N, N), complex)
+    h = np.empty((rank, N, N), complex)
+    for t in range(rank):
+        c = rng.standard_normal(6)
+        g[t] = (1 + 0.5 * c[0] * x1 + c[1] * x2 ** 2) * np.exp(1j * (c[2] * x1 - x2))
+        h[t] = 1 / (1 + 0.1 * (c[3] * k1 / N) ** 2 + (k2 / N + c[4]) ** 2) * np.exp(1j * c[5] * k1 / N)
+    return g, h
+
+
 def mixed_batch(seed: int, n: int = 32) -> list[dict]:
     """Uneven batch of problems: N ~ U{128,256,512,1024}, tolerance ~
     U{1e-2, 1e-4, 1e-6}, (eta1, eta2) ~ U[0, 0.3]^2, per-problem f seeds."""
