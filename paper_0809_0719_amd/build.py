@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libfio.so")
 SOURCES = ["fio_plan.cpp", "fio_kernels_fwd.hip", "fio_kernels_adj.hip", "fio_kernels_init.hip", "fio_kernels_term.hip",
            "fio_kernels_mfma.hip",
            "fio_kernels_tan.hip", "fio_kernels_amp.hip",
-           "fio_kernels_direct.hip", "fio_batch.cpp",
+           "fio_kernels_direct.hip", "fio_batch.cpp", "fio_kernels_swadj.hip",
            "fio_kernels_3d.hip", "fio3.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -87,13 +87,15 @@ __global__ __launch_bounds__(256) void k_plevel_mfma(Geom g, PhaseDev ph, Tables
         ctb[t] = c_;
         stb[t] = s_;
     }
-    // zero the padding k' in [2q, KP) of the staged rows once
-    for (int i = tid; i < 4 * Q * RT * (KP - 2 * Q); i += 256) {
-        const int kp = 2 * Q + i % (KP - 2 * Q), rest = i / (KP - 2 * Q);
-        const int r = rest % RT, rest2 = rest / RT;
-        const int t2 = rest2 % Q, jj = rest2 / Q;
-        Wre[jj][t2][r][kp] = (__bf16)0.0f;
-        Wim[jj][t2][r][kp] = (__bf16)0.0f;
+    // zero the padding k' in [2q, KP) of the staged rows once (none when 2q = KP)
+    if constexpr (KP > 2 * Q) {
+        for (int i = tid; i < 4 * Q * RT * (KP - 2 * Q); i += 256) {
+            const int kp = 2 * Q + i % (KP - 2 * Q), rest = i / (KP - 2 * Q);
+            const int r = rest % RT, rest2 = rest / RT;
+            const int t2 = rest2 % Q, jj = rest2 / Q;
+            Wre[jj][t2][r][kp] = (__bf16)0.0f;
+            Wim[jj][t2][r][kp] = (__bf16)0.0f;
+        }
     }
     __syncthreads();
     // kernel values of output j, shared by all right-hand sides

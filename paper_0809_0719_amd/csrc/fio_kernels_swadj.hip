@@ -1,0 +1,203 @@
+// Adjoint switch (the conjugate transpose of eq:alg2m) for batches of
+// right-hand sides on the matrix cores, complex64.
+//
+// For a pair (A, B) at the switch level the polar nodes of B are
+// p_s = (rho0 + h_s1, theta_s2) with h_{q-1-j} = -h_j (Chebyshev symmetry), and
+// with G(t, s2) = Phi(x^A_t, e(theta_s2)) homogeneity gives
+//     E(x^A_t, p_s) = b(t, s2) d_s1(t, s2),  b = e^{2 pi i rho0 G},  d_j = e^{2 pi i h_j G},
+// d_{q-1-j} = conj d_j and d_H = 1 for odd q (H = floor(q/2)).  The adjoint
+//     delta'_s = sum_t conj E(x^A_t, p_s) delta_t
+// is therefore, for each direction node s2 and with y_t = conj b(t, s2) delta_t,
+//     delta'_(j, s2)     = P_j - i Q_j,   delta'_(q-1-j, s2) = P_j + i Q_j,
+//     delta'_(H, s2)     = sum_t y_t (odd q),
+//     P_j = sum_t Re d_j(t, s2) y_t,   Q_j = sum_t Im d_j(t, s2) y_t:
+// a real (q x q^2) matrix R_s2 = [Re d_j; Im d_j; 1] times the (q^2 x nrhs)
+// complex matrix y.  That product runs as v_mfma_f32_16x16x4_f32 tiles: rows
+// k of R (q <= 16, one tile), reduction over t in steps of 4, columns the
+// right-hand sides (16 per wave, real and imaginary parts in two tiles).
+//
+// A workgroup (4 waves, 64 right-hand sides) takes a few (pair, chunk) items
+// in turn.  Per item: the weights are staged through LDS (coalesced rows in,
+// then each lane keeps its operand column, q^2/4 values, in registers for all
+// q direction nodes), the tables R and conj b (one phase and 1 + floor(q/2)
+// exponentials per (t, s2), as in the vector kernel) are built in LDS, the
+// outputs of every s2 go back to the staging buffer and leave as coalesced
+// rows.  The next item's weights are loaded into registers while the current
+// one computes.  In place: an item's stores go to the rows its own loads read.
+//
+// MFMA lane layout (16x16x4, 64 lanes): A operand lane l holds A[l%16][l/16],
+// B operand B[l/16][l%16], accumulator element v of lane l is D[4(l/16)+v][l%16].
+#include <hip/hip_runtime.h>
+
+#include "fio_kernels_common.h"
+
+namespace fio {
+
+namespace {
+
+using f32x4 = __attribute__((ext_vector_type(4))) float;
+
+constexpr int SA_RC = 64;   // right-hand sides per item (16 per wave)
+constexpr int SA_PPW = 8;   // items per workgroup
+
+template <int Q>
+constexpr int sa_srow() { return (Q * Q) | 1; }  // odd row stride (complex) of the staging buffer
+template <int Q>
+constexpr int sa_kt() { return (Q * Q + 3) / 4; }  // reduction steps over t
+template <int Q>
+constexpr int sa_lpt() { return (SA_RC * Q * Q + NT - 1) / NT; }  // staged values per thread
+
+}  // namespace
+
+bool switch_adj_mfma_supported(int q, int nrhs) { return q >= QMIN && q <= 9 && nrhs >= 32; }
+
+template <int Q>
+__global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Tables tb, cpx<float> *__restrict__ w,
+                                                         int nrhs, size_t plane, size_t nitems, int nchunk) {
+    constexpr int QQ = Q * Q, H = Q / 2;
+    constexpr int KT = sa_kt<Q>(), SROW = sa_srow<Q>(), LPT = sa_lpt<Q>();
+    __shared__ float Rt[Q][QQ][Q];          // [s2][t][k]: Re d_j (k = 2j), Im d_j (k = 2j + 1), 1 (k = 2H)
+    __shared__ cpx<float> Bt[Q][QQ];        // conj b(t, s2)
+    __shared__ cpx<float> stage[SA_RC][SROW];
+    __shared__ double sx[2][Q], cx[2][Q], cth[Q], sth[Q];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    const int lA = g.lm, lB = g.L - g.lm;
+    const size_t nBl = (size_t)1 << (2 * lB);
+    const size_t item0 = linear_block() * SA_PPW;
+    if (item0 >= nitems) return;  // whole workgroup
+    const int nit = (int)min((size_t)SA_PPW, nitems - item0);
+    const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
+    double hz[H > 0 ? H : 1];
+#pragma unroll
+    for (int j = 0; j < H; ++j) hz[j] = g.rho_scale * ldexp(tb.z[j], -lB);
+
+    // staged element e = r * q^2 + t of an item: right-hand side r, node t
+    cpx<float> pf[LPT];
+    auto fetch = [&](size_t item) {
+        const size_t pair = item / nchunk;
+        const int q0 = (int)(item - pair * nchunk) * SA_RC;
+#pragma unroll
+        for (int k = 0; k < LPT; ++k) {
+            const int e = tid + k * NT, r = e / QQ, t = e - r * QQ;
+            pf[k] = (e < SA_RC * QQ && q0 + r < nrhs) ? w[(size_t)(q0 + r) * plane + pair * QQ + t]
+                                                     : cpx<float>{0.f, 0.f};
+        }
+    };
+    fetch(item0);
+    for (int it = 0; it < nit; ++it) {
+        const size_t item = item0 + it, pair = item / nchunk;
+        const int q0 = (int)(item - pair * nchunk) * SA_RC;
+        const uint32_t mB = (uint32_t)(pair & (nBl - 1)), mA = (uint32_t)(pair >> (2 * lB));
+        int b1, b2, a1, a2;
+        morton_decode(mB, b1, b2);
+        morton_decode(mA, a1, a2);
+
+        lds_barrier();  // the previous item's stores and table readers are done
+#pragma unroll
+        for (int k = 0; k < LPT; ++k) {
+            const int e = tid + k * NT, r = e / QQ, t = e - r * QQ;
+            if (e < SA_RC * QQ) stage[r][t] = pf[k];
+        }
+        if (it + 1 < nit) fetch(item + 1);
+        if (tid < 2 * Q) {  // A's nodes per dimension
+            const int d = tid / Q, t = tid - d * Q;
+            double s_ = 0, c_ = 1;
+            if (ell) sincospi(2.0 * box_node(d ? a2 : a1, lA, tb.z[t]), &s_, &c_);
+            sx[d][t] = s_;
+            cx[d][t] = c_;
+        } else if (tid < 3 * Q) {  // B's direction nodes
+            const int t = tid - 2 * Q;
+            double s_, c_;
+            sincospi(2.0 * box_node(b2, lB, tb.z[t]), &s_, &c_);
+            cth[t] = c_;
+            sth[t] = s_;
+        }
+        lds_barrier();
+        {
+            const double r0 = g.rho_scale * box_centre(b1, lB);
+            for (int i = tid; i < Q * QQ; i += NT) {
+                const int s2 = i / QQ, t = i - s2 * QQ, t1 = t / Q, t2 = t - t1 * Q;
+                const XP xp = make_xp_sc(ph, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]), sx[0][t1],
+                                         cx[0][t1], sx[1][t2], cx[1][t2]);
+                const double G = phase_dir(xp, cth[s2], sth[s2]);
+                const cpx<float> b = cis<float>(r0 * G);
+                Bt[s2][t] = {b.re, -b.im};
+#pragma unroll
+                for (int j = 0; j < H; ++j) {
+                    const cpx<float> d = cis<float>(hz[j] * G);
+                    Rt[s2][t][2 * j] = d.re;
+                    Rt[s2][t][2 * j + 1] = d.im;
+                }
+                if (Q & 1) Rt[s2][t][2 * H] = 1.f;
+            }
+        }
+        // this lane's operand column: right-hand side 16 wv + lo, nodes t = 4 ks + hi
+        const int rl = 16 * wv + lo;
+        cpx<float> dreg[KT];
+#pragma unroll
+        for (int ks = 0; ks < KT; ++ks) {
+            const int t = 4 * ks + hi;
+            dreg[ks] = t < QQ ? stage[rl][t] : cpx<float>{0.f, 0.f};
+        }
+        lds_barrier();  // tables built; every operand read from the staging buffer is done
+        const int kr = lo < Q ? lo : Q - 1;  // this lane's row k of R (rows k >= q are zero)
+#pragma unroll 1
+        for (int s2 = 0; s2 < Q; ++s2) {
+            f32x4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KT; ++ks) {
+                const int t = 4 * ks + hi, tc = t < QQ ? t : QQ - 1;
+                const float a = (lo < Q && t < QQ) ? Rt[s2][tc][kr] : 0.f;
+                const cpx<float> y = cmul(Bt[s2][tc], dreg[ks]);  // zero where t >= q^2 (dreg is)
+                zr = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y.re, zr, 0, 0, 0);
+                zi = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y.im, zi, 0, 0, 0);
+            }
+            // lane holds rows k = 4 hi + v of column rl: (P_j, Q_j) at v = 0, 1 and v = 2, 3
+#pragma unroll
+            for (int v = 0; v < 4; v += 2) {
+                const int k = 4 * hi + v, j = k >> 1;
+                if (j < H) {
+                    const float pr = zr[v], pi = zi[v], qr = zr[v + 1], qi = zi[v + 1];
+                    stage[rl][j * Q + s2] = {pr + qi, pi - qr};
+                    stage[rl][(Q - 1 - j) * Q + s2] = {pr - qi, pi + qr};
+                } else if ((Q & 1) && k == 2 * H) {
+                    stage[rl][H * Q + s2] = {zr[v], zi[v]};
+                }
+            }
+        }
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < LPT; ++k) {
+            const int e = tid + k * NT, r = e / QQ, t = e - r * QQ;
+            if (e < SA_RC * QQ && q0 + r < nrhs) w[(size_t)(q0 + r) * plane + pair * QQ + t] = stage[r][t];
+        }
+    }
+}
+
+hipError_t launch_switch_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs,
+                                  size_t plane, hipStream_t st) {
+    if (!switch_adj_mfma_supported(g.q, nrhs)) return hipErrorInvalidValue;
+    const size_t npairs = (size_t)1 << (2 * g.L);
+    const int nchunk = (nrhs + SA_RC - 1) / SA_RC;
+    const size_t nitems = npairs * (size_t)nchunk;
+    const size_t nblk = (nitems + SA_PPW - 1) / SA_PPW;
+#define L_SAM(Q)                                                                                          \
+    hipLaunchKernelGGL((k_switch_adj_mm<Q>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, (cpx<float> *)w, nrhs, \
+                       plane, nitems, nchunk);
+    switch (g.q) {
+        case 3: L_SAM(3) break;
+        case 4: L_SAM(4) break;
+        case 5: L_SAM(5) break;
+        case 6: L_SAM(6) break;
+        case 7: L_SAM(7) break;
+        case 8: L_SAM(8) break;
+        case 9: L_SAM(9) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef L_SAM
+    return hipGetLastError();
+}
+
+}  // namespace fio
