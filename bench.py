@@ -59,6 +59,19 @@ def mfma_init_flops(N: int, q: int) -> float:
     return 2.0 * q * q * 128 * N * N
 
 
+def mfma_switch_adj_flops(N: int, q: int) -> float:
+    """FP32 flops of the matrix-core adjoint switch for one right-hand side:
+    per pair and direction node, a real (q x q^2) matrix times the real and
+    imaginary parts of q^2 weights, 2 x 2 q^3 flops; q nodes, N^2 pairs."""
+    return 4.0 * q ** 4 * N * N
+
+
+def switch_adj_on_mfma(q: int, nrhs: int) -> bool:
+    """The library runs the adjoint switch of complex64 batches of 32 or more
+    right-hand sides at q <= 9 on the matrix cores (fio_apply_adjoint)."""
+    return q <= 9 and nrhs >= 32
+
+
 def lane_ops(kind: str, N: int, q: int, s: int, nrhs: int, rc_switch: int = 8, rc_switch_adj: int = 4) -> float:
     n2 = float(N) * N
     h = q // 2
@@ -387,8 +400,13 @@ def main():
             per_launch_rhs = R * args.steps / k_n
         else:
             per_launch_rhs = R
+        mfma_flops = None
         if kind in ("init", "init_adj") and per_launch_rhs > 1:
-            ops = per_launch_rhs * mfma_init_flops(N, q)
+            mfma_flops = mfma_init_flops(N, q)
+        elif kind == "switch_adj" and switch_adj_on_mfma(q, per_launch_rhs):
+            mfma_flops = mfma_switch_adj_flops(N, q)
+        if mfma_flops is not None:
+            ops = per_launch_rhs * mfma_flops
             ach = ops / (avg_ms * 1e-3) / 1e12
             per_kind[kind] = {"avg_ms": avg_ms, "launches": k_n, "bound": "mfma", "unit": "TFLOP/s",
                               "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS, "frac": ach / MFMA_FP32_PEAK_TFLOPS}

@@ -38,7 +38,7 @@ namespace {
 using f32x4 = __attribute__((ext_vector_type(4))) float;
 
 constexpr int SA_RC = 64;   // right-hand sides per item (16 per wave)
-constexpr int SA_PPW = 8;   // items per workgroup
+constexpr int SA_PPW = 16;  // items per workgroup
 
 template <int Q>
 constexpr int sa_srow() { return (Q * Q) | 1; }  // odd row stride (complex) of the staging buffer
@@ -73,16 +73,27 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
 #pragma unroll
     for (int j = 0; j < H; ++j) hz[j] = g.rho_scale * ldexp(tb.z[j], -lB);
 
-    // staged element e = r * q^2 + t of an item: right-hand side r, node t
+    // staged element e = tid + k NT = r q^2 + t of an item (right-hand side r,
+    // node t), walked incrementally: NT = DR q^2 + DT
+    constexpr int DR = NT / QQ, DT = NT - DR * QQ;
+    const int r_0 = tid / QQ, t_0 = tid - r_0 * QQ;
     cpx<float> pf[LPT];
     auto fetch = [&](size_t item) {
         const size_t pair = item / nchunk;
         const int q0 = (int)(item - pair * nchunk) * SA_RC;
+        const cpx<float> *src = w + (size_t)(q0 + r_0) * plane + pair * QQ + t_0;
+        int r = r_0, t = t_0;
 #pragma unroll
         for (int k = 0; k < LPT; ++k) {
-            const int e = tid + k * NT, r = e / QQ, t = e - r * QQ;
-            pf[k] = (e < SA_RC * QQ && q0 + r < nrhs) ? w[(size_t)(q0 + r) * plane + pair * QQ + t]
-                                                     : cpx<float>{0.f, 0.f};
+            pf[k] = (r < SA_RC && q0 + r < nrhs) ? *src : cpx<float>{0.f, 0.f};
+            r += DR;
+            t += DT;
+            src += DR * plane + DT;
+            if (t >= QQ) {
+                t -= QQ;
+                ++r;
+                src += plane - QQ;
+            }
         }
     };
     fetch(item0);
@@ -95,10 +106,18 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
         morton_decode(mA, a1, a2);
 
         lds_barrier();  // the previous item's stores and table readers are done
+        {
+            int r = r_0, t = t_0;
 #pragma unroll
-        for (int k = 0; k < LPT; ++k) {
-            const int e = tid + k * NT, r = e / QQ, t = e - r * QQ;
-            if (e < SA_RC * QQ) stage[r][t] = pf[k];
+            for (int k = 0; k < LPT; ++k) {
+                if (r < SA_RC) stage[r][t] = pf[k];
+                r += DR;
+                t += DT;
+                if (t >= QQ) {
+                    t -= QQ;
+                    ++r;
+                }
+            }
         }
         if (it + 1 < nit) fetch(item + 1);
         if (tid < 2 * Q) {  // A's nodes per dimension
@@ -116,21 +135,29 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
         }
         lds_barrier();
         {
+            // thread (t, group of SG direction nodes): A's node data once per t
+            constexpr int SG = (QQ * Q + NT - 1) / NT > 1 ? (Q + (NT / QQ) - 1) / (NT / QQ) : 1;
             const double r0 = g.rho_scale * box_centre(b1, lB);
-            for (int i = tid; i < Q * QQ; i += NT) {
-                const int s2 = i / QQ, t = i - s2 * QQ, t1 = t / Q, t2 = t - t1 * Q;
+            for (int i = tid; i < QQ * ((Q + SG - 1) / SG); i += NT) {
+                const int sg = i / QQ, t = i - sg * QQ, t1 = t / Q, t2 = t - t1 * Q;
                 const XP xp = make_xp_sc(ph, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]), sx[0][t1],
                                          cx[0][t1], sx[1][t2], cx[1][t2]);
-                const double G = phase_dir(xp, cth[s2], sth[s2]);
-                const cpx<float> b = cis<float>(r0 * G);
-                Bt[s2][t] = {b.re, -b.im};
+#pragma unroll 1
+                for (int u = 0; u < SG; ++u) {
+                    const int s2 = sg * SG + u;
+                    if (s2 < Q) {
+                        const double G = phase_dir(xp, cth[s2], sth[s2]);
+                        const cpx<float> b = cis<float>(r0 * G);
+                        Bt[s2][t] = {b.re, -b.im};
 #pragma unroll
-                for (int j = 0; j < H; ++j) {
-                    const cpx<float> d = cis<float>(hz[j] * G);
-                    Rt[s2][t][2 * j] = d.re;
-                    Rt[s2][t][2 * j + 1] = d.im;
+                        for (int j = 0; j < H; ++j) {
+                            const cpx<float> d = cis<float>(hz[j] * G);
+                            Rt[s2][t][2 * j] = d.re;
+                            Rt[s2][t][2 * j + 1] = d.im;
+                        }
+                        if (Q & 1) Rt[s2][t][2 * H] = 1.f;
+                    }
                 }
-                if (Q & 1) Rt[s2][t][2 * H] = 1.f;
             }
         }
         // this lane's operand column: right-hand side 16 wv + lo, nodes t = 4 ks + hi
@@ -142,14 +169,17 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
             dreg[ks] = t < QQ ? stage[rl][t] : cpx<float>{0.f, 0.f};
         }
         lds_barrier();  // tables built; every operand read from the staging buffer is done
-        const int kr = lo < Q ? lo : Q - 1;  // this lane's row k of R (rows k >= q are zero)
+        // this lane's row k of R; the rows k >= q of the tile read row q - 1
+        // instead of zeros: they only feed accumulator rows that are never
+        // stored.  Nodes t >= q^2 contribute nothing: their weights are zero.
+        const int kr = lo < Q ? lo : Q - 1;
 #pragma unroll 1
         for (int s2 = 0; s2 < Q; ++s2) {
             f32x4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < KT; ++ks) {
                 const int t = 4 * ks + hi, tc = t < QQ ? t : QQ - 1;
-                const float a = (lo < Q && t < QQ) ? Rt[s2][tc][kr] : 0.f;
+                const float a = Rt[s2][tc][kr];
                 const cpx<float> y = cmul(Bt[s2][tc], dreg[ks]);  // zero where t >= q^2 (dreg is)
                 zr = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y.re, zr, 0, 0, 0);
                 zi = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y.im, zi, 0, 0, 0);
@@ -168,10 +198,21 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
             }
         }
         lds_barrier();
+        {
+            cpx<float> *dst = w + (size_t)(q0 + r_0) * plane + pair * QQ + t_0;
+            int r = r_0, t = t_0;
 #pragma unroll
-        for (int k = 0; k < LPT; ++k) {
-            const int e = tid + k * NT, r = e / QQ, t = e - r * QQ;
-            if (e < SA_RC * QQ && q0 + r < nrhs) w[(size_t)(q0 + r) * plane + pair * QQ + t] = stage[r][t];
+            for (int k = 0; k < LPT; ++k) {
+                if (r < SA_RC && q0 + r < nrhs) *dst = stage[r][t];
+                r += DR;
+                t += DT;
+                dst += DR * plane + DT;
+                if (t >= QQ) {
+                    t -= QQ;
+                    ++r;
+                    dst += plane - QQ;
+                }
+            }
         }
     }
 }
