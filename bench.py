@@ -59,16 +59,17 @@ def mfma_init_flops(N: int, q: int) -> float:
     return 2.0 * q * q * 128 * N * N
 
 
-def mfma_switch_adj_flops(N: int, q: int) -> float:
-    """FP32 flops of the matrix-core adjoint switch for one right-hand side:
-    per pair and direction node, a real (q x q^2) matrix times the real and
-    imaginary parts of q^2 weights, 2 x 2 q^3 flops; q nodes, N^2 pairs."""
+def mfma_switch_flops(N: int, q: int) -> float:
+    """FP32 flops of the matrix-core switch (either direction) for one
+    right-hand side: per pair and direction node, a real q^2-by-q product
+    with the real and imaginary parts of the weights, 2 x 2 q^3 flops; q
+    nodes, N^2 pairs."""
     return 4.0 * q ** 4 * N * N
 
 
-def switch_adj_on_mfma(q: int, nrhs: int) -> bool:
-    """The library runs the adjoint switch of complex64 batches of 32 or more
-    right-hand sides at q <= 9 on the matrix cores (fio_apply_adjoint)."""
+def switch_on_mfma(q: int, nrhs: int) -> bool:
+    """The library runs the switch and its adjoint of complex64 batches of 32
+    or more right-hand sides at q <= 9 on the matrix cores."""
     return q <= 9 and nrhs >= 32
 
 
@@ -403,8 +404,8 @@ def main():
         mfma_flops = None
         if kind in ("init", "init_adj") and per_launch_rhs > 1:
             mfma_flops = mfma_init_flops(N, q)
-        elif kind == "switch_adj" and switch_adj_on_mfma(q, per_launch_rhs):
-            mfma_flops = mfma_switch_adj_flops(N, q)
+        elif kind in ("switch", "switch_adj") and switch_on_mfma(q, per_launch_rhs):
+            mfma_flops = mfma_switch_flops(N, q)
         if mfma_flops is not None:
             ops = per_launch_rhs * mfma_flops
             ach = ops / (avg_ms * 1e-3) / 1e12

@@ -160,8 +160,9 @@ int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream);
  * initialisation^H), which approximates f(k) = sum_x exp(-2 pi i Phi(x,k))
  * u(x).  Same layouts and rules as fio_apply with the roles of f, u swapped.
  * Chunks of 32 or more complex64 right-hand sides at q <= 9 take the switch^H
- * on the matrix cores (FP32 products and sums in another order: the results
- * agree with the single-right-hand-side path to FP32 rounding). */
+ * on the matrix cores, as fio_apply takes the switch (FP32 products and sums
+ * in another order: the results agree with the single-right-hand-side path
+ * to FP32 rounding). */
 int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, void *stream);
 
 /* Forward butterfly with its derivatives with respect to the velocity

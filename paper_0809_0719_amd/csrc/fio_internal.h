@@ -92,9 +92,13 @@ hipError_t launch_init_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables 
                                 const void *ktab, const void *etab, const void *w, void *f, int nrhs,
                                 size_t plane, hipStream_t st);
 
-// Adjoint switch on the matrix cores (fio_kernels_swadj.hip), complex64,
-// q <= 9 and nrhs >= 32: in place on the weights at level lm, planes `plane`
-// apart; the same operator as the vector kernel of launch_switch_adj.
+// Switch and adjoint switch on the matrix cores (fio_kernels_swadj.hip),
+// complex64, q <= 9 and nrhs >= 32: in place on the weights at level lm,
+// planes `plane` apart; the same operators as the vector kernels of
+// launch_switch and launch_switch_adj.
+bool switch_mfma_supported(int q, int nrhs);
+hipError_t launch_switch_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs, size_t plane,
+                              hipStream_t st);
 bool switch_adj_mfma_supported(int q, int nrhs);
 hipError_t launch_switch_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs,
                                   size_t plane, hipStream_t st);

@@ -776,6 +776,7 @@ static hipError_t xlevel_t(const Geom &g, const PhaseDev &ph, const Tables &tb, 
 template <typename T>
 static hipError_t switch_t(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs, size_t plane,
                            hipStream_t st) {
+    if (sizeof(T) == 4 && switch_mfma_supported(g.q, nrhs)) return launch_switch_mfma(g, ph, tb, w, nrhs, plane, st);
     const size_t npairs = (size_t)1 << (2 * g.L);
 #define L_SW(Q)                                                                                      \
     {                                                                                                \

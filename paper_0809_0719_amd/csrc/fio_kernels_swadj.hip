@@ -217,6 +217,248 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
     }
 }
 
+// Forward switch on the matrix cores, complex64: with the same R and
+//     X_s2 = [S_j; i D_j; delta_H],  S_j = delta_(j, s2) + delta_(q-1-j, s2),
+//     D_j = delta_(j, s2) - delta_(q-1-j, s2),
+// delta'_t = sum_s2 b(t, s2) (R_s2 X_s2)_t: per direction node a real
+// (q^2 x q) by complex (q x nrhs) product on the matrix cores (rows t padded
+// to a multiple of 16, reduction k padded to a multiple of 4 with zero rows of
+// X), then the remodulation by b and the sum over s2 on the vector ALUs, in
+// registers.  Items, staging and prefetch as in the adjoint above; the staged
+// inputs stay in LDS for the whole item (X is formed from them per node) and
+// the outputs go back through the same buffer once every node is done.
+bool switch_mfma_supported(int q, int nrhs) { return q >= QMIN && q <= 9 && nrhs >= 32; }
+
+template <int Q>
+__global__ __launch_bounds__(NT, 2) void k_switch_mm(Geom g, PhaseDev ph, Tables tb, cpx<float> *__restrict__ w,
+                                                     int nrhs, size_t plane, size_t nitems, int nchunk) {
+    constexpr int QQ = Q * Q, H = Q / 2;
+    constexpr int SROW = sa_srow<Q>(), LPT = sa_lpt<Q>();
+    constexpr int TT = (QQ + 15) / 16;  // row tiles of t
+    constexpr int KS = (Q + 3) / 4;     // reduction steps over k
+    constexpr int TH = (TT + 1) / 2;    // row tiles per accumulator group
+    __shared__ float Rt[Q][QQ][Q];      // [s2][t][k] as in the adjoint
+    __shared__ cpx<float> Bt[Q][QQ];    // b(t, s2)
+    __shared__ cpx<float> stage[SA_RC][SROW];
+    __shared__ double sx[2][Q], cx[2][Q], cth[Q], sth[Q];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    const int lA = g.lm, lB = g.L - g.lm;
+    const size_t nBl = (size_t)1 << (2 * lB);
+    const size_t item0 = linear_block() * SA_PPW;
+    if (item0 >= nitems) return;  // whole workgroup
+    const int nit = (int)min((size_t)SA_PPW, nitems - item0);
+    const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
+    double hz[H > 0 ? H : 1];
+#pragma unroll
+    for (int j = 0; j < H; ++j) hz[j] = g.rho_scale * ldexp(tb.z[j], -lB);
+
+    constexpr int DR = NT / QQ, DT = NT - DR * QQ;
+    const int r_0 = tid / QQ, t_0 = tid - r_0 * QQ;
+    cpx<float> pf[LPT];
+    auto fetch = [&](size_t item) {
+        const size_t pair = item / nchunk;
+        const int q0 = (int)(item - pair * nchunk) * SA_RC;
+        const cpx<float> *src = w + (size_t)(q0 + r_0) * plane + pair * QQ + t_0;
+        int r = r_0, t = t_0;
+#pragma unroll
+        for (int k = 0; k < LPT; ++k) {
+            pf[k] = (r < SA_RC && q0 + r < nrhs) ? *src : cpx<float>{0.f, 0.f};
+            r += DR;
+            t += DT;
+            src += DR * plane + DT;
+            if (t >= QQ) {
+                t -= QQ;
+                ++r;
+                src += plane - QQ;
+            }
+        }
+    };
+    if (Q & 1)  // the middle column of R: d_H = 1 for every (s2, t)
+        for (int i = tid; i < Q * QQ; i += NT) (&Rt[0][0][0])[i * Q + 2 * H] = 1.f;
+    // this lane's reduction rows k = 4 ks + hi of X: the pair j = k / 2 (S_j for
+    // even k, i D_j for odd k), the middle row k = 2H, zero past q
+    const int rl = 16 * wv + lo;
+    fetch(item0);
+    for (int it = 0; it < nit; ++it) {
+        const size_t item = item0 + it, pair = item / nchunk;
+        const int q0 = (int)(item - pair * nchunk) * SA_RC;
+        const uint32_t mB = (uint32_t)(pair & (nBl - 1)), mA = (uint32_t)(pair >> (2 * lB));
+        int b1, b2, a1, a2;
+        morton_decode(mB, b1, b2);
+        morton_decode(mA, a1, a2);
+
+        lds_barrier();  // the previous item's stores and table readers are done
+        {
+            int r = r_0, t = t_0;
+#pragma unroll
+            for (int k = 0; k < LPT; ++k) {
+                if (r < SA_RC) stage[r][t] = pf[k];
+                r += DR;
+                t += DT;
+                if (t >= QQ) {
+                    t -= QQ;
+                    ++r;
+                }
+            }
+        }
+        if (it + 1 < nit) fetch(item + 1);
+        if (tid < 2 * Q) {  // A's nodes per dimension
+            const int d = tid / Q, t = tid - d * Q;
+            double s_ = 0, c_ = 1;
+            if (ell) sincospi(2.0 * box_node(d ? a2 : a1, lA, tb.z[t]), &s_, &c_);
+            sx[d][t] = s_;
+            cx[d][t] = c_;
+        } else if (tid < 3 * Q) {  // B's direction nodes
+            const int t = tid - 2 * Q;
+            double s_, c_;
+            sincospi(2.0 * box_node(b2, lB, tb.z[t]), &s_, &c_);
+            cth[t] = c_;
+            sth[t] = s_;
+        }
+        lds_barrier();
+        {
+            constexpr int SG = (QQ * Q + NT - 1) / NT > 1 ? (Q + (NT / QQ) - 1) / (NT / QQ) : 1;
+            const double r0 = g.rho_scale * box_centre(b1, lB);
+            for (int i = tid; i < QQ * ((Q + SG - 1) / SG); i += NT) {
+                const int sg = i / QQ, t = i - sg * QQ, t1 = t / Q, t2 = t - t1 * Q;
+                const XP xp = make_xp_sc(ph, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]), sx[0][t1],
+                                         cx[0][t1], sx[1][t2], cx[1][t2]);
+#pragma unroll 1
+                for (int u = 0; u < SG; ++u) {
+                    const int s2 = sg * SG + u;
+                    if (s2 < Q) {
+                        const double G = phase_dir(xp, cth[s2], sth[s2]);
+                        Bt[s2][t] = cis<float>(r0 * G);
+#pragma unroll
+                        for (int j = 0; j < H; ++j) {
+                            const cpx<float> d = cis<float>(hz[j] * G);
+                            Rt[s2][t][2 * j] = d.re;
+                            Rt[s2][t][2 * j + 1] = d.im;
+                        }
+                    }
+                }
+            }
+        }
+        lds_barrier();  // tables built
+        cpx<float> acc[TT][4];
+#pragma unroll
+        for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[tt][v] = {0.f, 0.f};
+#pragma unroll 1
+        for (int s2 = 0; s2 < Q; ++s2) {
+            // B operand: X[k][rl] for k = 4 ks + hi
+            float xr[KS], xi[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + hi, j = k >> 1;
+                const int ja = j < H ? j : H, jb = j < H ? Q - 1 - j : H;  // (H, H): the middle row
+                const cpx<float> da = stage[rl][ja * Q + s2], db = stage[rl][jb * Q + s2];
+                float vr, vi;
+                if (k < 2 * H) {
+                    if (k & 1) {  // i D_j
+                        vr = db.im - da.im;
+                        vi = da.re - db.re;
+                    } else {  // S_j
+                        vr = da.re + db.re;
+                        vi = da.im + db.im;
+                    }
+                } else {
+                    const bool mid = (Q & 1) && k == 2 * H;
+                    vr = mid ? da.re : 0.f;
+                    vi = mid ? da.im : 0.f;
+                }
+                xr[ks] = vr;
+                xi[ks] = vi;
+            }
+            // row tiles in groups of TH (fewer accumulators live at once)
+#pragma unroll
+            for (int t0 = 0; t0 < TT; t0 += TH) {
+                f32x4 zr[TH], zi[TH];
+#pragma unroll
+                for (int u = 0; u < TH; ++u) zr[u] = zi[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    // A operand R[t][k] for t = 16 tt + lo, k = 4 ks + hi: clamped reads
+                    // (rows t >= q^2 feed accumulator rows that are never used; columns
+                    // k >= q meet zero rows of X)
+                    const int kc = 4 * ks + hi < Q ? 4 * ks + hi : Q - 1;
+#pragma unroll
+                    for (int u = 0; u < TH; ++u) {
+                        if (t0 + u < TT) {
+                            const int t = 16 * (t0 + u) + lo, tc = t < QQ ? t : QQ - 1;
+                            const float a = Rt[s2][tc][kc];
+                            zr[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xr[ks], zr[u], 0, 0, 0);
+                            zi[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xi[ks], zi[u], 0, 0, 0);
+                        }
+                    }
+                }
+                // remodulate: rows t = 16 tt + 4 hi + v of column rl
+#pragma unroll
+                for (int u = 0; u < TH; ++u)
+                    if (t0 + u < TT) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int t = 16 * (t0 + u) + 4 * hi + v, tc = t < QQ ? t : QQ - 1;
+                            cfma(acc[t0 + u][v], Bt[s2][tc], cpx<float>{zr[u][v], zi[u][v]});
+                        }
+                    }
+            }
+        }
+        lds_barrier();  // every read of the staged inputs is done
+#pragma unroll
+        for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int t = 16 * tt + 4 * hi + v;
+                if (t < QQ) stage[rl][t] = acc[tt][v];
+            }
+        lds_barrier();
+        {
+            cpx<float> *dst = w + (size_t)(q0 + r_0) * plane + pair * QQ + t_0;
+            int r = r_0, t = t_0;
+#pragma unroll
+            for (int k = 0; k < LPT; ++k) {
+                if (r < SA_RC && q0 + r < nrhs) *dst = stage[r][t];
+                r += DR;
+                t += DT;
+                dst += DR * plane + DT;
+                if (t >= QQ) {
+                    t -= QQ;
+                    ++r;
+                    dst += plane - QQ;
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_switch_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs,
+                              size_t plane, hipStream_t st) {
+    if (!switch_mfma_supported(g.q, nrhs)) return hipErrorInvalidValue;
+    const size_t npairs = (size_t)1 << (2 * g.L);
+    const int nchunk = (nrhs + SA_RC - 1) / SA_RC;
+    const size_t nitems = npairs * (size_t)nchunk;
+    const size_t nblk = (nitems + SA_PPW - 1) / SA_PPW;
+#define L_SFM(Q)                                                                                           \
+    hipLaunchKernelGGL((k_switch_mm<Q>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, (cpx<float> *)w, nrhs, \
+                       plane, nitems, nchunk);
+    switch (g.q) {
+        case 3: L_SFM(3) break;
+        case 4: L_SFM(4) break;
+        case 5: L_SFM(5) break;
+        case 6: L_SFM(6) break;
+        case 7: L_SFM(7) break;
+        case 8: L_SFM(8) break;
+        case 9: L_SFM(9) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef L_SFM
+    return hipGetLastError();
+}
+
 hipError_t launch_switch_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs,
                                   size_t plane, hipStream_t st) {
     if (!switch_adj_mfma_supported(g.q, nrhs)) return hipErrorInvalidValue;

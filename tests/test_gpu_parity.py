@@ -368,6 +368,23 @@ def test_full_size_batched_parity_in_the_benchmark_configuration():
 
 @pytest.mark.parametrize("nr", [33, 65])
 @pytest.mark.parametrize("q", [3, 4, 5, 6, 7, 8, 9])
+def test_matrix_core_switch(q, nr):
+    """The forward switch of batches of 32 or more complex64 right-hand sides
+    at q <= 9 on the matrix cores, against the single-RHS forward (vector
+    switch), as for the adjoint below."""
+    import paper_0809_0719_amd as fio
+    N = 32
+    one = fio.Plan(N, q, fio.Phase(), dtype=torch.complex64)
+    many = fio.Plan(N, q, fio.Phase(), dtype=torch.complex64, nrhs_max=nr)
+    F = _dev(white_noise(N, 90 + q, nrhs=nr), torch.complex64)
+    U = many.apply(F)
+    for r in (0, 17, 32, nr - 1):
+        e = rel_l2(U[r].cpu().numpy(), one.apply(F[r]).cpu().numpy())
+        assert e <= 2e-6, (r, e)
+
+
+@pytest.mark.parametrize("nr", [33, 65])
+@pytest.mark.parametrize("q", [3, 4, 5, 6, 7, 8, 9])
 def test_matrix_core_adjoint_switch(q, nr):
     """Batches of 32 or more complex64 right-hand sides at q <= 9 take the
     adjoint switch on the matrix cores (chunks of 64: 33 leaves 31 columns
