@@ -51,41 +51,57 @@ constexpr int sa_lpt() { return (SA_RC * Q * Q + NT - 1) / NT; }  // staged valu
 
 bool switch_adj_mfma_supported(int q, int nrhs) { return q >= QMIN && q <= 9 && nrhs >= 32; }
 
+// The adjoint takes each item in two halves of 32 right-hand sides (8 per
+// wave, real and imaginary parts of one right-hand side in adjacent columns,
+// so a lane forms only its part of y), with the pair's tables built once for
+// both halves: the smaller staging buffer lets three workgroups share a CU.
+constexpr int SH_RC = SA_RC / 2;  // right-hand sides per half item
+
 template <int Q>
-__global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Tables tb, cpx<float> *__restrict__ w,
+constexpr int sh_lpt() { return (SH_RC * Q * Q + NT - 1) / NT; }
+
+template <int Q>
+__global__ __launch_bounds__(NT, 3) void k_switch_adj_mm(Geom g, PhaseDev ph, Tables tb, cpx<float> *__restrict__ w,
                                                          int nrhs, size_t plane, size_t nitems, int nchunk) {
     constexpr int QQ = Q * Q, H = Q / 2;
-    constexpr int KT = sa_kt<Q>(), SROW = sa_srow<Q>(), LPT = sa_lpt<Q>();
+    constexpr int KT = sa_kt<Q>(), SROW = sa_srow<Q>(), LPT = sh_lpt<Q>();
     __shared__ float Rt[Q][QQ][Q];          // [s2][t][k]: Re d_j (k = 2j), Im d_j (k = 2j + 1), 1 (k = 2H)
     __shared__ cpx<float> Bt[Q][QQ];        // conj b(t, s2)
-    __shared__ cpx<float> stage[SA_RC][SROW];
+    __shared__ cpx<float> stage[SH_RC][SROW];
     __shared__ double sx[2][Q], cx[2][Q], cth[Q], sth[Q];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int lo = lane & 15, hi = lane >> 4;
     const int lA = g.lm, lB = g.L - g.lm;
     const size_t nBl = (size_t)1 << (2 * lB);
-    const size_t item0 = linear_block() * SA_PPW;
-    if (item0 >= nitems) return;  // whole workgroup
-    const int nit = (int)min((size_t)SA_PPW, nitems - item0);
+    // half items h = 2 item + half; a workgroup takes 2 SA_PPW of them in turn
+    const size_t nhalf = 2 * nitems;
+    const size_t h0 = linear_block() * (2 * SA_PPW);
+    if (h0 >= nhalf) return;  // whole workgroup
+    const int nh = (int)min((size_t)(2 * SA_PPW), nhalf - h0);
     const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
     double hz[H > 0 ? H : 1];
 #pragma unroll
     for (int j = 0; j < H; ++j) hz[j] = g.rho_scale * ldexp(tb.z[j], -lB);
 
-    // staged element e = tid + k NT = r q^2 + t of an item (right-hand side r,
+    // staged element e = tid + k NT = r q^2 + t of a half (right-hand side r,
     // node t), walked incrementally: NT = DR q^2 + DT
     constexpr int DR = NT / QQ, DT = NT - DR * QQ;
     const int r_0 = tid / QQ, t_0 = tid - r_0 * QQ;
+    auto first_rhs = [&](size_t h, size_t &pair) {
+        const size_t item = h >> 1;
+        pair = item / nchunk;
+        return (int)(item - pair * nchunk) * SA_RC + (int)(h & 1) * SH_RC;
+    };
     cpx<float> pf[LPT];
-    auto fetch = [&](size_t item) {
-        const size_t pair = item / nchunk;
-        const int q0 = (int)(item - pair * nchunk) * SA_RC;
+    auto fetch = [&](size_t h) {
+        size_t pair;
+        const int q0 = first_rhs(h, pair);
         const cpx<float> *src = w + (size_t)(q0 + r_0) * plane + pair * QQ + t_0;
         int r = r_0, t = t_0;
 #pragma unroll
         for (int k = 0; k < LPT; ++k) {
-            pf[k] = (r < SA_RC && q0 + r < nrhs) ? *src : cpx<float>{0.f, 0.f};
+            pf[k] = (r < SH_RC && q0 + r < nrhs) ? *src : cpx<float>{0.f, 0.f};
             r += DR;
             t += DT;
             src += DR * plane + DT;
@@ -96,21 +112,26 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
             }
         }
     };
-    fetch(item0);
-    for (int it = 0; it < nit; ++it) {
-        const size_t item = item0 + it, pair = item / nchunk;
-        const int q0 = (int)(item - pair * nchunk) * SA_RC;
-        const uint32_t mB = (uint32_t)(pair & (nBl - 1)), mA = (uint32_t)(pair >> (2 * lB));
-        int b1, b2, a1, a2;
-        morton_decode(mB, b1, b2);
-        morton_decode(mA, a1, a2);
+    if (Q & 1)  // the middle row of R: d_H = 1 for every (s2, t)
+        for (int i = tid; i < Q * QQ; i += NT) (&Rt[0][0][0])[i * Q + 2 * H] = 1.f;
+    // this lane's column: right-hand side rl of the half, part 0 (real) or 1
+    // (imaginary); its row k = lo of R (rows k >= q read row q - 1: they only
+    // feed accumulator rows that are never stored)
+    const int rl = 8 * wv + (lo >> 1), part = lo & 1;
+    const int kr = lo < Q ? lo : Q - 1;
+    fetch(h0);
+    size_t built = ~(size_t)0;  // the pair whose tables are in LDS
+    for (int ih = 0; ih < nh; ++ih) {
+        const size_t h = h0 + ih;
+        size_t pair;
+        const int q0 = first_rhs(h, pair);
 
-        lds_barrier();  // the previous item's stores and table readers are done
+        lds_barrier();  // the previous half's stores (and, for a new pair, table readers) are done
         {
             int r = r_0, t = t_0;
 #pragma unroll
             for (int k = 0; k < LPT; ++k) {
-                if (r < SA_RC) stage[r][t] = pf[k];
+                if (r < SH_RC) stage[r][t] = pf[k];
                 r += DR;
                 t += DT;
                 if (t >= QQ) {
@@ -119,22 +140,27 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
                 }
             }
         }
-        if (it + 1 < nit) fetch(item + 1);
-        if (tid < 2 * Q) {  // A's nodes per dimension
-            const int d = tid / Q, t = tid - d * Q;
-            double s_ = 0, c_ = 1;
-            if (ell) sincospi(2.0 * box_node(d ? a2 : a1, lA, tb.z[t]), &s_, &c_);
-            sx[d][t] = s_;
-            cx[d][t] = c_;
-        } else if (tid < 3 * Q) {  // B's direction nodes
-            const int t = tid - 2 * Q;
-            double s_, c_;
-            sincospi(2.0 * box_node(b2, lB, tb.z[t]), &s_, &c_);
-            cth[t] = c_;
-            sth[t] = s_;
-        }
-        lds_barrier();
-        {
+        if (ih + 1 < nh) fetch(h + 1);
+        if (pair != built) {  // uniform
+            built = pair;
+            const uint32_t mB = (uint32_t)(pair & (nBl - 1)), mA = (uint32_t)(pair >> (2 * lB));
+            int b1, b2, a1, a2;
+            morton_decode(mB, b1, b2);
+            morton_decode(mA, a1, a2);
+            if (tid < 2 * Q) {  // A's nodes per dimension
+                const int d = tid / Q, t = tid - d * Q;
+                double s_ = 0, c_ = 1;
+                if (ell) sincospi(2.0 * box_node(d ? a2 : a1, lA, tb.z[t]), &s_, &c_);
+                sx[d][t] = s_;
+                cx[d][t] = c_;
+            } else if (tid < 3 * Q) {  // B's direction nodes
+                const int t = tid - 2 * Q;
+                double s_, c_;
+                sincospi(2.0 * box_node(b2, lB, tb.z[t]), &s_, &c_);
+                cth[t] = c_;
+                sth[t] = s_;
+            }
+            lds_barrier();
             // thread (t, group of SG direction nodes): A's node data once per t
             constexpr int SG = (QQ * Q + NT - 1) / NT > 1 ? (Q + (NT / QQ) - 1) / (NT / QQ) : 1;
             const double r0 = g.rho_scale * box_centre(b1, lB);
@@ -155,45 +181,47 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
                             Rt[s2][t][2 * j] = d.re;
                             Rt[s2][t][2 * j + 1] = d.im;
                         }
-                        if (Q & 1) Rt[s2][t][2 * H] = 1.f;
                     }
                 }
             }
         }
-        // this lane's operand column: right-hand side 16 wv + lo, nodes t = 4 ks + hi
-        const int rl = 16 * wv + lo;
-        cpx<float> dreg[KT];
+        // this lane's weights d (right-hand side rl, nodes t = 4 ks + hi) as the
+        // pair (dp, dq) with part(c d) = c.re dp + c.im dq: (d.re, -d.im) for
+        // the real part, (d.im, d.re) for the imaginary part
+        float dp[KT], dq[KT];
 #pragma unroll
         for (int ks = 0; ks < KT; ++ks) {
             const int t = 4 * ks + hi;
-            dreg[ks] = t < QQ ? stage[rl][t] : cpx<float>{0.f, 0.f};
+            const cpx<float> d = t < QQ ? stage[rl][t] : cpx<float>{0.f, 0.f};
+            dp[ks] = part ? d.im : d.re;
+            dq[ks] = part ? d.re : -d.im;
         }
         lds_barrier();  // tables built; every operand read from the staging buffer is done
-        // this lane's row k of R; the rows k >= q of the tile read row q - 1
-        // instead of zeros: they only feed accumulator rows that are never
-        // stored.  Nodes t >= q^2 contribute nothing: their weights are zero.
-        const int kr = lo < Q ? lo : Q - 1;
+        float *const srow = &stage[rl][0].re;  // the lane's output row, as floats
 #pragma unroll 1
         for (int s2 = 0; s2 < Q; ++s2) {
-            f32x4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
+            f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < KT; ++ks) {
                 const int t = 4 * ks + hi, tc = t < QQ ? t : QQ - 1;
                 const float a = Rt[s2][tc][kr];
-                const cpx<float> y = cmul(Bt[s2][tc], dreg[ks]);  // zero where t >= q^2 (dreg is)
-                zr = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y.re, zr, 0, 0, 0);
-                zi = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y.im, zi, 0, 0, 0);
+                const cpx<float> c = Bt[s2][tc];  // y = c d, zero where t >= q^2
+                const float y = fmaf(c.re, dp[ks], c.im * dq[ks]);
+                z = __builtin_amdgcn_mfma_f32_16x16x4f32(a, y, z, 0, 0, 0);
             }
-            // lane holds rows k = 4 hi + v of column rl: (P_j, Q_j) at v = 0, 1 and v = 2, 3
+            // rows k = 4 hi + v of this lane's column: P_j (v = 0, 2) and Q_j
+            // (v = 1, 3) in this lane's part; the partner lane holds the other
 #pragma unroll
             for (int v = 0; v < 4; v += 2) {
                 const int k = 4 * hi + v, j = k >> 1;
+                const float qo = __shfl_xor(z[v + 1], 1);  // the other part of Q_j
                 if (j < H) {
-                    const float pr = zr[v], pi = zi[v], qr = zr[v + 1], qi = zi[v + 1];
-                    stage[rl][j * Q + s2] = {pr + qi, pi - qr};
-                    stage[rl][(Q - 1 - j) * Q + s2] = {pr - qi, pi + qr};
+                    // real parts: P_j.re +- Q_j.im; imaginary parts: P_j.im -+ Q_j.re
+                    const float p = z[v];
+                    srow[2 * (j * Q + s2) + part] = part ? p - qo : p + qo;
+                    srow[2 * ((Q - 1 - j) * Q + s2) + part] = part ? p + qo : p - qo;
                 } else if ((Q & 1) && k == 2 * H) {
-                    stage[rl][H * Q + s2] = {zr[v], zi[v]};
+                    srow[2 * (H * Q + s2) + part] = z[v];
                 }
             }
         }
@@ -203,7 +231,7 @@ __global__ __launch_bounds__(NT, 2) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
             int r = r_0, t = t_0;
 #pragma unroll
             for (int k = 0; k < LPT; ++k) {
-                if (r < SA_RC && q0 + r < nrhs) *dst = stage[r][t];
+                if (r < SH_RC && q0 + r < nrhs) *dst = stage[r][t];
                 r += DR;
                 t += DT;
                 dst += DR * plane + DT;
