@@ -141,12 +141,13 @@ __global__ __launch_bounds__(NT, 3) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
             }
         }
         if (ih + 1 < nh) fetch(h + 1);
-        if (pair != built) {  // uniform
-            built = pair;
-            const uint32_t mB = (uint32_t)(pair & (nBl - 1)), mA = (uint32_t)(pair >> (2 * lB));
-            int b1, b2, a1, a2;
-            morton_decode(mB, b1, b2);
-            morton_decode(mA, a1, a2);
+        const bool newpair = pair != built;  // uniform
+        built = pair;
+        const uint32_t mB = (uint32_t)(pair & (nBl - 1)), mA = (uint32_t)(pair >> (2 * lB));
+        int b1, b2, a1, a2;
+        morton_decode(mB, b1, b2);
+        morton_decode(mA, a1, a2);
+        if (newpair) {
             if (tid < 2 * Q) {  // A's nodes per dimension
                 const int d = tid / Q, t = tid - d * Q;
                 double s_ = 0, c_ = 1;
@@ -160,7 +161,9 @@ __global__ __launch_bounds__(NT, 3) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
                 cth[t] = c_;
                 sth[t] = s_;
             }
-            lds_barrier();
+        }
+        lds_barrier();  // the staged weights (and a new pair's node data) are complete
+        if (newpair) {
             // thread (t, group of SG direction nodes): A's node data once per t
             constexpr int SG = (QQ * Q + NT - 1) / NT > 1 ? (Q + (NT / QQ) - 1) / (NT / QQ) : 1;
             const double r0 = g.rho_scale * box_centre(b1, lB);
