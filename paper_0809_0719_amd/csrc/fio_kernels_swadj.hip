@@ -14,16 +14,18 @@
 // a real (q x q^2) matrix R_s2 = [Re d_j; Im d_j; 1] times the (q^2 x nrhs)
 // complex matrix y.  That product runs as v_mfma_f32_16x16x4_f32 tiles: rows
 // k of R (q <= 16, one tile), reduction over t in steps of 4, columns the
-// right-hand sides (16 per wave, real and imaginary parts in two tiles).
+// real and imaginary parts of 8 right-hand sides per wave.
 //
-// A workgroup (4 waves, 64 right-hand sides) takes a few (pair, chunk) items
-// in turn.  Per item: the weights are staged through LDS (coalesced rows in,
-// then each lane keeps its operand column, q^2/4 values, in registers for all
-// q direction nodes), the tables R and conj b (one phase and 1 + floor(q/2)
-// exponentials per (t, s2), as in the vector kernel) are built in LDS, the
-// outputs of every s2 go back to the staging buffer and leave as coalesced
-// rows.  The next item's weights are loaded into registers while the current
-// one computes.  In place: an item's stores go to the rows its own loads read.
+// A workgroup (4 waves) takes 16 (pair, 64-RHS chunk) items in turn, each as
+// two halves of 32 right-hand sides.  Per half: the weights are staged
+// through LDS (coalesced rows in, then each lane keeps its operand column,
+// q^2/4 values, in registers for all q direction nodes), the outputs of
+// every s2 go back to the staging buffer and leave as coalesced rows; the
+// tables R and conj b (one phase and 1 + floor(q/2) exponentials per (t, s2),
+// as in the vector kernel) are built in LDS once per pair.  The next half's
+// weights are loaded into registers while the current one computes.  In
+// place: a half's stores go to the rows its own loads read.  The forward
+// switch below shares the tables, the items and the staging.
 //
 // MFMA lane layout (16x16x4, 64 lanes): A operand lane l holds A[l%16][l/16],
 // B operand B[l/16][l%16], accumulator element v of lane l is D[4(l/16)+v][l%16].
