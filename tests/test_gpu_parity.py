@@ -336,7 +336,8 @@ def test_full_size_batched_parity_in_the_benchmark_configuration():
     """N = 1024, q = 9, eq:ex1, complex64, nrhs_max = 64 and 64 right-hand
     sides (the inputs the benchmark times, white noise seed 3): the batched
     kernels (matrix-core initialisation for two right-hand sides per pass,
-    hoisted levels, 8-wide switch chunks, one-lane-per-RHS termination)
+    hoisted levels, the switch and its adjoint on the matrix cores,
+    one-lane-per-RHS termination)
     against the oracle's restricted pass on two sampled leaf boxes for the
     first and the last right-hand side; and the batched adjoint through the
     identity sum_r <v_r, B f_r> = sum_r <B^H v_r, f_r>, which holds at any
