@@ -11,10 +11,14 @@ batch of `nrhs` right-hand sides: the whole pass (initialisation, p-levels,
 switch, x-levels, termination) in both directions.  `value` counts every
 forward and every adjoint application of one right-hand side as one apply.
 
-Printed on one JSON line: throughput, the roofline of the dominant kernel
-(its time measured with HIP events recorded on the launch stream inside the
-timed region), the relative error eq:err against the FP64 direct sum on 256
-sampled points, and the CPU baseline: the direct-sum oracle timed on the
+Printed on one JSON line: throughput; the roofline of every kernel and of
+the dominant one -- algorithmic bytes and flops (the method's definition) per
+launch over its time measured with HIP events recorded on the launch stream
+inside the timed region, against the published HBM and FP32 peaks -- and the
+end-to-end fraction; the relative error eq:err against the FP64 direct sum
+for the first, middle and last right-hand side, forward on 256 sampled points
+x and adjoint on 256 sampled frequencies k, with the verdict against the
+metric's tolerance; and the CPU baseline: the direct-sum oracle timed on the
 host on 3072 sampled points (about 10 s) and extrapolated to all N^2 points.
 """
 from __future__ import annotations
@@ -31,80 +35,73 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FIO applies/sec at N=1024,q=9, rel err ≤1e-4; batched+adjoint vs plain"
+METRIC_TOL = 1e-4
 
-# MI355X peaks
+# MI355X published peaks: HBM3E bandwidth and dense FP32 (matrix cores; the
+# vector ALUs reach the same figure only with packed FP32, which the library
+# does not use)
 HBM_PEAK_GBS = 8000.0
-# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
-# (an FP32 or FP64 FMA is one lane-op; sine, cosine, square root and
-# reciprocal square root issue at quarter rate: 4 lane-ops each)
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 157.3
+CSIZE = 8  # bytes of one complex64 value
 
 
-# Algorithmic VALU lane-operations per launch of every kernel kind.  Unit
-# costs: an exponential of an FP64-reduced phase = 12 (FP64 product, round,
-# subtract, convert = 4; sine + cosine at quarter rate = 8); a direction or
-# Cartesian phase = 9 (2 FMA, 2 mul, 1 add, square root = 4); a real-by-
-# complex multiply-add = 2; a complex product or multiply-add = 4.  Kernel
-# values shared by a chunk of right-hand sides are counted once per chunk.
-EXP, PHS, CRMAC, CMUL = 12, 9, 2, 4
+def algorithmic_work(kind: str, N: int, q: int, s: int, nrhs: int):
+    """(HBM bytes, FP32 flops) one launch of `kind` needs by the method's
+    definition, for `nrhs` right-hand sides in complex64.
 
-# dense FP32 MFMA peak of MI355X
-MFMA_FP32_PEAK_TFLOPS = 157.3
+    Bytes: every level, switch, initialisation and termination reads its
+    input and writes its output once -- weights are N^2 q^2 complex values
+    per right-hand side, sources and potentials N^2 (tables of a few KB and
+    the initialisation's stored kernel values are not counted).
 
-
-def mfma_init_flops(N: int, q: int) -> float:
-    """FP32 flops of the initialisation's contraction for one right-hand
-    side: per box B a real (q^2 x n_p) by complex (n_p x 64) product, i.e.
-    2 x q^2 x n_p x 128 flops, and the n_p sum to N^2 over the boxes."""
-    return 2.0 * q * q * 128 * N * N
-
-
-def mfma_switch_flops(N: int, q: int) -> float:
-    """FP32 flops of the matrix-core switch (either direction) for one
-    right-hand side: per pair and direction node, a real q^2-by-q product
-    with the real and imaginary parts of the weights, 2 x 2 q^3 flops; q
-    nodes, N^2 pairs."""
-    return 4.0 * q ** 4 * N * N
-
-
-def switch_on_mfma(q: int, nrhs: int) -> bool:
-    """The library runs the switch and its adjoint of complex64 batches of 32
-    or more right-hand sides at q <= 9 on the matrix cores."""
-    return q <= 9 and nrhs >= 32
-
-
-def lane_ops(kind: str, N: int, q: int, s: int, nrhs: int, rc_switch: int = 8, rc_switch_adj: int = 4) -> float:
+    Flops (real; a real-by-complex multiply-add is 4, a complex multiply-add
+    8, a complex product 6), per pair and right-hand side:
+      level (either half, either direction): the one-dimensional passes of
+        the Kronecker sum, 6 q^3 real-by-complex multiply-adds, and 5 q^2
+        complex products (prefactors and remodulation);
+      switch: the q^2 x q^2 kernel of a pair (8 q^4 flops as a dense complex
+        product), counted as the kernels execute it once the Chebyshev
+        symmetry z_{q-1-j} = -z_j has halved it: 4 q^4 flops;
+      initialisation: 4^s q^2 real-by-complex multiply-adds per source (the
+        Lagrange weights against the kernel-weighted sources of every box A),
+        q^2 complex products per pair;
+      termination: q^2 2^s + q 4^s real-by-complex multiply-adds and
+        q^2 + 4^s complex products per box pair."""
     n2 = float(N) * N
-    h = q // 2
-    m = 1 << s
-    nA = 4 ** s
+    W = n2 * q * q
     if kind in ("plevel", "plevel_adj", "xlevel", "xlevel_adj"):
-        shared = 5 * q * q * EXP + 3 * q * PHS if kind.startswith("p") else 5 * q * q * EXP + 2.5 * q * q * PHS
-        per_rhs = 6 * q ** 3 * CRMAC + 5 * q * q * CMUL
-        return n2 * (shared + nrhs * per_rhs)
+        return 2 * W * CSIZE * nrhs, n2 * nrhs * (24 * q ** 3 + 30 * q * q)
     if kind in ("switch", "switch_adj"):
-        rc = 1 if nrhs == 1 else (rc_switch if kind == "switch" else rc_switch_adj)
-        chunks = -(-nrhs // rc)
-        shared = q ** 3 * (PHS + (1 + h) * EXP)
-        # forward: h paired updates (4 FMA) and one complex multiply-add per
-        # (t, s2); adjoint: one conjugate product, h pairs of real-by-complex
-        # multiply-adds and, for odd q, the middle row's addition
-        per_rhs = q ** 3 * (4 * h + 4 + (2 * (q & 1) if kind == "switch_adj" else 0))
-        return n2 * (chunks * shared + nrhs * per_rhs)
+        return 2 * W * CSIZE * nrhs, n2 * nrhs * 4 * q ** 4
     if kind in ("init", "init_adj"):
-        # per (A, source): phase + exponential + product + q^2 + q multiply-adds;
-        # per (A, B box): q^2 remodulation exponentials and products
-        per_rhs = nA * n2 * (PHS + EXP + CMUL + (q * q + q) * CRMAC) + nA * (n2 / nA) * q * q * (EXP + CMUL)
-        return nrhs * per_rhs
+        return (W + n2) * CSIZE * nrhs, n2 * nrhs * (4 * 4 ** s * q * q + 6 * q * q)
     if kind in ("term", "term_adj"):
-        # per (A, B): q^2 prefactors, the two 1-D passes, m^2 factors E(x, p0(B));
-        # their kernel values (q^2 + m^2 phases and exponentials) once per
-        # launch when several right-hand sides share them
-        pairs = n2
-        shared = (q * q + m * m) * (PHS + EXP)
-        per_rhs = q * q * CMUL + (q * q * m + m * m * q) * CRMAC + m * m * CMUL
-        return pairs * (shared * (1 if nrhs > 1 else nrhs) + nrhs * per_rhs)
+        m = 1 << s
+        return (W + n2) * CSIZE * nrhs, n2 * nrhs * (4 * (q * q * m + q * m * m) + 6 * (q * q + m * m))
     raise ValueError(kind)
+
+
+def roofline_of(kind: str, avg_ms: float, launches: int, N: int, q: int, s: int, nrhs: int) -> dict:
+    """Both bounds of one kernel kind: achieved GB/s against the HBM peak and
+    achieved TFLOP/s against the FP32 peak; the binding one is the larger
+    fraction (the bound the kernel is closest to)."""
+    nbytes, flops = algorithmic_work(kind, N, q, s, nrhs)
+    sec = avg_ms * 1e-3
+    gbs, tfs = nbytes / sec / 1e9, flops / sec / 1e12
+    hf, ff = gbs / HBM_PEAK_GBS, tfs / FP32_PEAK_TFLOPS
+    out = {"avg_ms": avg_ms, "launches": launches, "nrhs": nrhs, "bytes": nbytes, "flops": flops,
+           "hbm_gbs": gbs, "hbm_frac": hf, "fp32_tflops": tfs, "fp32_frac": ff,
+           "bound_ms": max(nbytes / (HBM_PEAK_GBS * 1e9), flops / (FP32_PEAK_TFLOPS * 1e12)) * 1e3}
+    if hf >= ff:
+        out.update(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hf)
+    else:
+        out.update(bound="mfma" if kind in MFMA_KINDS else "alu", achieved=tfs, peak=FP32_PEAK_TFLOPS,
+                   unit="TFLOP/s", frac=ff)
+    return out
+
+
+# kernel kinds that run on the matrix cores in the benchmark's configuration
+MFMA_KINDS = ("init", "init_adj", "switch", "switch_adj")
 
 
 def traffic_from_profiles(kernel: str, config: dict):
@@ -387,55 +384,55 @@ def main():
     torch.cuda.synchronize()
     plain = nplain / (time.perf_counter() - t2)
 
-    # roofline of every kernel kind, and of the dominant one (largest share of
-    # the timed region): algorithmic work per launch / average launch time.
-    # VALU kernels: lane-operations against the VALU issue rate; the
-    # initialisation on the matrix cores: its contraction's FP32 flops against
-    # the FP32 MFMA peak.
+    # roofline of every kernel kind and of the dominant one (largest share of
+    # the timed region): algorithmic bytes and flops per launch (the method's
+    # definition, see algorithmic_work) / the average launch time measured with
+    # HIP events on the launch stream, against the published peaks
     per_kind = {}
     for kind, (k_ms, k_n) in prof.items():
         if kind == "tables":
             continue
-        avg_ms = k_ms / k_n
-        if kind in ("init", "init_adj", "term", "term_adj"):
-            per_launch_rhs = R * args.steps / k_n
-        else:
-            per_launch_rhs = R
-        mfma_flops = None
-        if kind in ("init", "init_adj") and per_launch_rhs > 1:
-            mfma_flops = mfma_init_flops(N, q)
-        elif kind in ("switch", "switch_adj") and switch_on_mfma(q, per_launch_rhs):
-            mfma_flops = mfma_switch_flops(N, q)
-        if mfma_flops is not None:
-            ops = per_launch_rhs * mfma_flops
-            ach = ops / (avg_ms * 1e-3) / 1e12
-            per_kind[kind] = {"avg_ms": avg_ms, "launches": k_n, "bound": "mfma", "unit": "TFLOP/s",
-                              "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS, "frac": ach / MFMA_FP32_PEAK_TFLOPS}
-        else:
-            ops = lane_ops(kind, N, q, plan.s, per_launch_rhs)
-            ach = ops / (avg_ms * 1e-3) / 1e12
-            per_kind[kind] = {"avg_ms": avg_ms, "launches": k_n, "bound": "alu", "unit": "Tlane-op/s",
-                              "achieved": ach, "peak": VALU_PEAK_TOPS, "frac": ach / VALU_PEAK_TOPS}
+        # levels and switches take the whole chunk per launch; the
+        # initialisation and termination may take one right-hand side each
+        nr = R * args.steps / k_n if kind in ("init", "init_adj", "term", "term_adj") else R
+        per_kind[kind] = roofline_of(kind, k_ms / k_n, k_n, N, q, plan.s, nr)
     kind = max(per_kind, key=lambda k: prof[k][0])
     kk = per_kind[kind]
     roof = {"bound": kk["bound"], "kernel": f"k_{kind}", "achieved": kk["achieved"], "peak": kk["peak"],
             "unit": kk["unit"], "frac": kk["frac"],
             "traffic": traffic_from_profiles(f"k_{kind}", {"N": N, "q": q, "nrhs": R, "dtype": "complex64",
                                                           "contract": args.contract}),
+            "hbm_frac": kk["hbm_frac"], "fp32_frac": kk["fp32_frac"],
             "avg_ms": kk["avg_ms"], "launches": kk["launches"]}
+    # end to end: the time the bounds allow for one step / the measured step
+    bound_ms = sum(v["bound_ms"] * v["launches"] for v in per_kind.values()) / args.steps
+    roof["end_to_end_frac"] = bound_ms / ms_per_step
+    roof["end_to_end_bound_ms"] = bound_ms
 
-    # accuracy: eq:err on sampled points against the FP64 direct sum, and the CPU baseline
-    rows = sample_points(N, args.rows, seed=103)
-    u0 = u[0].cpu().numpy().reshape(-1)[rows]
-    rel_err = None
+    # accuracy: eq:err against the FP64 direct sum (the oracle's C loop) for
+    # right-hand sides 0, 31 and 63 -- forward on 256 sampled x, adjoint on
+    # 256 sampled k (the adjoint's input is the forward's output u) -- and the
+    # CPU baseline
+    errs = None
     cpu = None
+    meets = None
     if not args.no_cpu_baseline:
         from oracle import direct as D
         from oracle.build import build as build_oracle
         if not os.path.exists(os.path.join(ROOT, "oracle", "liborc_direct.so")):
             build_oracle()
-        ud = D.forward(N, D.Phase(), f_host[0], rows)
-        rel_err = D.rel_err(ud, u0.astype(np.complex128))
+        rows = sample_points(N, args.rows, seed=103)
+        cols = sample_points(N, args.rows, seed=105)
+        errs = {"forward": {}, "adjoint": {}, "points": args.rows}
+        for r in sorted({0, (R - 1) // 2, R - 1}):
+            ud = D.forward(N, D.Phase(), f_host[r], rows)
+            errs["forward"][str(r)] = D.rel_err(ud, u[r].cpu().numpy().reshape(-1)[rows].astype(np.complex128))
+            ur = u[r].cpu().numpy().astype(np.complex128)
+            gd = D.adjoint(N, D.Phase(), ur, cols)
+            errs["adjoint"][str(r)] = D.rel_err(gd, g[r].cpu().numpy().reshape(-1)[cols].astype(np.complex128))
+        worst = max(max(errs["forward"].values()), max(errs["adjoint"].values()))
+        errs["max"] = worst
+        meets = bool(worst <= METRIC_TOL)
         crow = sample_points(N, args.cpu_rows, seed=104)
         tc = time.perf_counter()
         D.forward(N, D.Phase(), f_host[0], crow)
@@ -454,7 +451,9 @@ def main():
                    "N": N, "q": q, "nrhs": R, "s": plan.s, "lm": plan.lm, "phase_dtype": "f64",
                    "weight_dtype": "f32", "contract": args.contract},
         "plain_forward_applies_per_s": plain,
-        "rel_err_vs_direct_sum": rel_err,
+        "rel_err_vs_direct_sum": errs,
+        "meets_metric_tolerance": meets,
+        "metric_tolerance": METRIC_TOL,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
         "kernel_roofline": per_kind,
         "roofline": roof,

@@ -148,12 +148,19 @@ int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info);
  *   f: device, nrhs x N x N complex (plan dtype), f[r][k1+N/2][k2+N/2].
  *      Read only.
  *   u: device, nrhs x N x N complex (plan dtype), u[r][i1][i2] = u_r(i1/N,
- *      i2/N).  Fully overwritten.  Must not overlap f.
+ *      i2/N).  Fully overwritten.  The byte ranges of f and u (nrhs N^2
+ *      complex values each) must not share a byte.
  *   nrhs >= 1 right-hand sides, processed in chunks of the plan's nrhs_max;
  *   within a chunk the kernel values of the levels and the switch are
  *   computed once and applied to every right-hand side.
- * Asynchronous on `stream`; FIO_EINVAL before any launch on bad arguments. */
-int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream);
+ *   dtype: FIO_C64 or FIO_C128, the element type of f and u as the caller
+ *      holds them; it must equal the plan's dtype (the weight buffers, the
+ *      tables and the kernels are sized and compiled for the plan's precision
+ *      when the plan is made, so a call cannot switch it).
+ * Asynchronous on `stream`; FIO_EINVAL before any launch on bad arguments
+ * (NULL pointers, nrhs < 1, a dtype other than the plan's, overlapping
+ * ranges). */
+int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, int dtype, void *stream);
 
 /* Adjoint butterfly f = B^H u: the exact conjugate transpose of the
  * forward pipeline (termination^H, x-levels^H, switch^H, p-levels^H,
@@ -163,7 +170,7 @@ int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream);
  * on the matrix cores, as fio_apply takes the switch (FP32 products and sums
  * in another order: the results agree with the single-right-hand-side path
  * to FP32 rounding). */
-int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, void *stream);
+int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, int dtype, void *stream);
 
 /* Forward butterfly with its derivatives with respect to the velocity
  * scalings a1, a2 of the ellipse phase (Sec. 5, eq:ex1 family), at the

@@ -426,8 +426,122 @@ class ButterflyModel:
                 f += np.conj(self.E(x01, x02, self.k1, self.k2)) * val
         return f.reshape(N, N)
 
-    def adjoint(self, u: np.ndarray) -> np.ndarray:
-        """f = B^H u (the exact conjugate transpose of ``apply``)."""
+    # ------------------------------------------------------------------------
+    # Adjoint restricted to some source boxes: the same conjugate-transposed
+    # formulas, with the loops taken over every box A of T_X and only over the
+    # boxes B of T_P that are ancestors of the chosen source boxes (in the
+    # adjoint the weights of pair (A, B) feed only the sources inside B).
+    # Weights of level l are dicts keyed by B at level L-l, each an array
+    # [a1, a2, t1, t2] over all A at level l.
+    # ------------------------------------------------------------------------
+    def terminate_adj_restricted(self, u: np.ndarray, act) -> dict:
+        N, q, L, s, z = self.N, self.q, self.L, self.s, self.z
+        lA = L - s
+        nA, m = 1 << lA, 1 << s
+        Tm = self.term_interp()                                             # (j, t)
+        xa = nodes(lA, np.arange(nA), z)                                    # (a, t)
+        xg = (np.arange(nA)[:, None] * m + np.arange(m)[None, :]) / N      # (a, j) grid points
+        U = np.asarray(u, dtype=np.complex128).reshape(nA, m, nA, m).transpose(0, 2, 1, 3)
+        d = {}
+        for b1, b2 in act:
+            p01, p02 = centre(s, b1), centre(s, b2)
+            post = self.E_p(xg[:, None, :, None], xg[None, :, None, :], p01, p02)      # (a1, a2, i, j)
+            W = np.einsum("ik,jl,xyij->xykl", Tm, Tm, np.conj(post) * U, optimize=True)
+            pre = self.E_p(xa[:, None, :, None], xa[None, :, None, :], p01, p02)        # (a1, a2, k, l)
+            d[(b1, b2)] = pre * W
+        return d
+
+    def x_level_adj_restricted(self, dout: dict, l: int, act_children) -> dict:
+        q, L, z = self.q, self.L, self.z
+        lB = L - l
+        nA = 1 << l
+        Xm = self.x_interp(l)                                               # (a, t, t')
+        xa = nodes(l, np.arange(nA), z)
+        xp = nodes(l - 1, np.arange(nA // 2), z)
+        din = {}
+        for c1, c2 in act_children:                                         # B_c at level lB+1
+            pc1, pc2 = centre(lB + 1, c1), centre(lB + 1, c2)
+            R = self.E_p(xa[:, None, :, None], xa[None, :, None, :], pc1, pc2)          # (a1, a2, t1, t2)
+            W = np.conj(R) * dout[(c1 >> 1, c2 >> 1)]
+            W = np.einsum("xik,yjl,xyij->xykl", Xm, Xm, W, optimize=True)             # parent nodes t'
+            W = W.reshape(nA // 2, 2, nA // 2, 2, q, q).sum(axis=(1, 3))              # sum over children A
+            pre = self.E_p(xp[:, None, :, None], xp[None, :, None, :], pc1, pc2)
+            din[(c1, c2)] = pre * W
+        return din
+
+    def switch_adj_restricted(self, d: dict) -> dict:
+        q, L, l, z = self.q, self.L, self.lm, self.z
+        lB = L - l
+        nA = 1 << l
+        xa = nodes(l, np.arange(nA), z)
+        X1 = xa[:, None, :, None, None, None]
+        X2 = xa[None, :, None, :, None, None]
+        out = {}
+        for (b1, b2), w in d.items():
+            pn1, pn2 = nodes(lB, b1, z), nodes(lB, b2, z)
+            K = self.E_p(X1, X2, pn1[None, None, None, None, :, None], pn2[None, None, None, None, None, :])
+            out[(b1, b2)] = np.einsum("xyijkl,xyij->xykl", np.conj(K), w, optimize=True)
+        return out
+
+    def p_level_adj_restricted(self, dout: dict, l: int, act_children) -> dict:
+        q, L, z = self.q, self.L, self.z
+        lB = L - l
+        nA = 1 << l
+        Lm = self.p_interp(lB)                                              # (b, c, t, t')
+        x0 = centre(l, np.arange(nA))
+        X1, X2 = x0[:, None, None, None], x0[None, :, None, None]
+        din = {}
+        for c1, c2 in act_children:                                         # B_c at level lB+1
+            b1, b2 = c1 >> 1, c2 >> 1
+            pn1, pn2 = nodes(lB, b1, z), nodes(lB, b2, z)
+            G = self.E_p(X1, X2, pn1[None, None, :, None], pn2[None, None, None, :]) * dout[(b1, b2)]
+            V = np.einsum("xyij,ik,jl->xykl", G, Lm[b1, c1 & 1], Lm[b2, c2 & 1], optimize=True)
+            pc1, pc2 = nodes(lB + 1, c1, z), nodes(lB + 1, c2, z)
+            pre = self.E_p(X1, X2, pc1[None, None, :, None], pc2[None, None, None, :])
+            V = np.conj(pre) * V
+            din[(c1, c2)] = V.reshape(nA // 2, 2, nA // 2, 2, q, q).sum(axis=(1, 3))
+        return din
+
+    def init_adj_restricted(self, d: dict) -> np.ndarray:
+        N, q, L, s, z = self.N, self.q, self.L, self.s, self.z
+        lB = L - s
+        nA, nB = 1 << s, 1 << lB
+        b1s, b2s = box_of(self.p1, lB), box_of(self.p2, lB)
+        x0 = centre(s, np.arange(nA))
+        X1, X2 = x0[:, None, None, None], x0[None, :, None, None]
+        f = np.zeros(N * N, dtype=np.complex128)
+        for (b1, b2), w in d.items():
+            j = np.nonzero((b1s == b1) & (b2s == b2))[0]                    # sources in B
+            if j.size == 0:
+                continue
+            u1 = (self.p1[j] - centre(lB, b1)) * nB
+            u2 = (self.p2[j] - centre(lB, b2)) * nB
+            lag = (lagrange(u1, z)[:, :, None] * lagrange(u2, z)[:, None, :]).reshape(j.size, q * q)
+            pn1, pn2 = nodes(lB, b1, z), nodes(lB, b2, z)
+            W = (self.E_p(X1, X2, pn1[None, None, :, None], pn2[None, None, None, :]) * w).reshape(nA * nA, q * q)
+            val = W @ lag.T                                                 # (A, source)
+            e = self.E(x0[:, None, None], x0[None, :, None], self.k1[j][None, None, :], self.k2[j][None, None, :])
+            f[j] = np.sum(np.conj(e).reshape(nA * nA, j.size) * val, axis=0)
+        return f.reshape(N, N)
+
+    def adjoint(self, u: np.ndarray, sources=None) -> np.ndarray:
+        """f = B^H u (the exact conjugate transpose of ``apply``).
+
+        ``sources``: optional list of boxes (b1, b2) at level L-s of T_P; then
+        only the pairs whose B is one of their ancestors are computed (the same
+        formulas, restricted loops), f is exact on the sources inside those
+        boxes and zero elsewhere."""
+        if sources is not None:
+            top = self.L - self.s
+            act = {m: sorted({(b1 >> (top - m), b2 >> (top - m)) for b1, b2 in sources})
+                   for m in range(self.s, top + 1)}
+            d = self.terminate_adj_restricted(u, act[self.s])
+            for l in range(self.L - self.s, self.lm, -1):
+                d = self.x_level_adj_restricted(d, l, act[self.L - l + 1])
+            d = self.switch_adj_restricted(d)
+            for l in range(self.lm, self.s, -1):
+                d = self.p_level_adj_restricted(d, l, act[self.L - l + 1])
+            return self.init_adj_restricted(d)
         d = self.terminate_adj(u)
         for l in range(self.L - self.s, self.lm, -1):
             d = self.x_level_adj(d, l)

@@ -108,8 +108,8 @@ def load_library():
     lib.fio_plan_ex.argtypes = [i, i, ctypes.POINTER(_CPhase), ctypes.POINTER(_COpts), ctypes.POINTER(vp)]
     lib.fio_set_phase.argtypes = [vp, ctypes.POINTER(_CPhase)]
     lib.fio_plan_get_info.argtypes = [vp, ctypes.POINTER(_CInfo)]
-    lib.fio_apply.argtypes = [vp, vp, vp, i, vp]
-    lib.fio_apply_adjoint.argtypes = [vp, vp, vp, i, vp]
+    lib.fio_apply.argtypes = [vp, vp, vp, i, i, vp]
+    lib.fio_apply_adjoint.argtypes = [vp, vp, vp, i, i, vp]
     lib.fio_apply_dphase.argtypes = [vp, vp, vp, vp, vp, i, vp]
     lib.fio_apply_amplitude.argtypes = [vp, vp, vp, vp, i, vp, vp]
     lib.fio_apply_amplitude_adjoint.argtypes = [vp, vp, vp, vp, i, vp, vp]
@@ -219,25 +219,50 @@ class Plan:
         nrhs = x.numel() // (self.N * self.N)
         return x, nrhs
 
+    def _out(self, out: torch.Tensor | None, like: torch.Tensor, name: str) -> torch.Tensor:
+        """The output tensor: a new one shaped like the input, or the caller's
+        ``out``, which the kernels overwrite through its data pointer -- so it
+        must have the input's shape and dtype, sit on the plan's device, be
+        contiguous and share no memory with the input."""
+        if out is None:
+            return torch.empty_like(like)
+        if not isinstance(out, torch.Tensor) or not out.is_cuda or out.device != self.device:
+            raise ValueError(f"{name} must be a tensor on {self.device}")
+        if out.dtype != like.dtype or out.shape != like.shape:
+            raise ValueError(f"{name} must be {like.dtype} of shape {tuple(like.shape)} "
+                             f"(got {out.dtype} {tuple(out.shape)})")
+        if not out.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        a0, a1 = out.data_ptr(), out.data_ptr() + out.numel() * out.element_size()
+        b0, b1 = like.data_ptr(), like.data_ptr() + like.numel() * like.element_size()
+        if a0 < b1 and b0 < a1:
+            raise ValueError(f"{name} must not overlap the input")
+        return out
+
+    @property
+    def _dtype_code(self) -> int:
+        return C64 if self.dtype == torch.complex64 else C128
+
     # -- the butterfly ------------------------------------------------------
     def apply(self, f: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """u = B f for f of shape (..., N, N) with f[..., k1+N/2, k2+N/2]."""
         f, nrhs = self._prep(f, "f")
-        u = torch.empty_like(f) if out is None else out
+        u = self._out(out, f, "out")
         if nrhs == 0:
             return u
         st = torch.cuda.current_stream(self.device).cuda_stream
-        _check(load_library().fio_apply(self._h, f.data_ptr(), u.data_ptr(), nrhs, st), "fio_apply")
+        _check(load_library().fio_apply(self._h, f.data_ptr(), u.data_ptr(), nrhs, self._dtype_code, st),
+               "fio_apply")
         return u
 
     def adjoint(self, u: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """f = B^H u for u of shape (..., N, N) with u[..., i1, i2] = u(i1/N, i2/N)."""
         u, nrhs = self._prep(u, "u")
-        f = torch.empty_like(u) if out is None else out
+        f = self._out(out, u, "out")
         if nrhs == 0:
             return f
         st = torch.cuda.current_stream(self.device).cuda_stream
-        _check(load_library().fio_apply_adjoint(self._h, u.data_ptr(), f.data_ptr(), nrhs, st),
+        _check(load_library().fio_apply_adjoint(self._h, u.data_ptr(), f.data_ptr(), nrhs, self._dtype_code, st),
                "fio_apply_adjoint")
         return f
 
@@ -271,7 +296,7 @@ class Plan:
         if nrhs != 1:
             raise ValueError("apply_amplitude takes one right-hand side")
         g, h, rank = self._prep_factors(g, h)
-        u = torch.empty_like(f) if out is None else out
+        u = self._out(out, f, "out")
         st = torch.cuda.current_stream(self.device).cuda_stream
         _check(load_library().fio_apply_amplitude(self._h, f.data_ptr(), g.data_ptr(), h.data_ptr(), rank,
                                                   u.data_ptr(), st), "fio_apply_amplitude")
@@ -284,7 +309,7 @@ class Plan:
         if nrhs != 1:
             raise ValueError("adjoint_amplitude takes one right-hand side")
         g, h, rank = self._prep_factors(g, h)
-        f = torch.empty_like(u) if out is None else out
+        f = self._out(out, u, "out")
         st = torch.cuda.current_stream(self.device).cuda_stream
         _check(load_library().fio_apply_amplitude_adjoint(self._h, u.data_ptr(), g.data_ptr(), h.data_ptr(),
                                                           rank, f.data_ptr(), st), "fio_apply_amplitude_adjoint")
@@ -410,7 +435,10 @@ class Batch:
         for p, x in zip(self.plans, xs):
             if x.numel() != p.N * p.N:
                 raise ValueError(f"{name}: one right-hand side per plan")
-        outs = [torch.empty_like(x) for x in xs] if outs is None else list(outs)
+        if outs is not None and len(outs) != len(xs):
+            raise ValueError(f"need {len(xs)} outputs, got {len(outs)}")
+        outs = [p._out(None if outs is None else outs[i], x, f"{name} output {i}")
+                for i, (p, x) in enumerate(zip(self.plans, xs))]
         n = len(xs)
         a = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
         b = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])

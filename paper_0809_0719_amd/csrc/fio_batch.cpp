@@ -16,6 +16,7 @@ using namespace fio;
 
 struct fio_batch_s {
     std::vector<fio_plan_t> plans;
+    std::vector<int> dtypes;     // each plan's dtype
     std::vector<int> order;      // plans by decreasing work
     std::vector<int> stream_of;  // internal stream of each plan
     std::vector<hipStream_t> streams;
@@ -82,6 +83,7 @@ int fio_batch_create(const fio_plan_t *plans, int n, int nstreams, fio_batch_t *
     if (!plans || n < 1 || n > 4096) return set_error(FIO_EINVAL, "need 1 <= n <= 4096 plans (got %d)", n);
     if (nstreams < 1 || nstreams > 16) return set_error(FIO_EINVAL, "nstreams must be in [1, 16] (got %d)", nstreams);
     std::vector<double> cost(n);
+    std::vector<int> dtypes(n);
     int dev = -1;
     for (int i = 0; i < n; ++i) {
         PlanView v;
@@ -91,12 +93,14 @@ int fio_batch_create(const fio_plan_t *plans, int n, int nstreams, fio_batch_t *
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return set_error(FIO_EINVAL, "plan %d appears twice (plans %d and %d)", i, j, i);
         cost[i] = (double)v.N * v.N * v.q * v.q * v.q;  // work per level ~ N^2 q^3
+        dtypes[i] = v.dtype;
     }
     int rc = use_device(dev);
     if (rc) return rc;
     fio_batch_s *b = new fio_batch_s;
     b->device = dev;
     b->plans.assign(plans, plans + n);
+    b->dtypes = dtypes;
     const int ns = std::min(nstreams, n);
     hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
     for (int j = 0; e == hipSuccess && j < ns; ++j) {
@@ -136,7 +140,7 @@ int fio_batch_apply(fio_batch_t batch, const void *const *f, void *const *u, voi
     int rc = use_device(batch->device);
     if (rc) return rc;
     return run_batch(batch, (hipStream_t)stream,
-                     [&](int i, hipStream_t s) { return fio_apply(batch->plans[i], f[i], u[i], 1, s); });
+                     [&](int i, hipStream_t s) { return fio_apply(batch->plans[i], f[i], u[i], 1, batch->dtypes[i], s); });
 }
 
 int fio_batch_apply_adjoint(fio_batch_t batch, const void *const *u, void *const *f, void *stream) {
@@ -149,7 +153,9 @@ int fio_batch_apply_adjoint(fio_batch_t batch, const void *const *u, void *const
     int rc = use_device(batch->device);
     if (rc) return rc;
     return run_batch(batch, (hipStream_t)stream,
-                     [&](int i, hipStream_t s) { return fio_apply_adjoint(batch->plans[i], u[i], f[i], 1, s); });
+                     [&](int i, hipStream_t s) {
+                         return fio_apply_adjoint(batch->plans[i], u[i], f[i], 1, batch->dtypes[i], s);
+                     });
 }
 
 int fio_batch_destroy(fio_batch_t batch) {
@@ -216,7 +222,7 @@ int fio_select_q(int N, const fio_phase_t *phase, const fio_plan_opts_t *opts, d
             plan = nullptr;
             if ((rc = fio_plan_ex(N, q, phase, opts, &plan))) break;
         }
-        if ((rc = fio_apply(plan, f, u, 1, nullptr))) break;
+        if ((rc = fio_apply(plan, f, u, 1, v.dtype, nullptr))) break;
         // the butterfly at the sampled targets: gather on the host
         std::vector<double> full;
         {

@@ -147,6 +147,28 @@ int check_plan(fio_plan_t plan) {
     return FIO_OK;
 }
 
+// Whether the byte ranges [a, a + na) and [b, b + nb) share a byte.
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+// Arguments of fio_apply / fio_apply_adjoint: non-NULL, nrhs >= 1, the
+// caller's dtype equal to the plan's, and input and output ranges (nrhs
+// planes of N^2 complex values each) disjoint.
+int check_apply_args(fio_plan_t plan, const void *in, void *out, int nrhs, int dtype, const char *names) {
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!in || !out) return fail(FIO_EINVAL, "%s must be non-NULL device pointers", names);
+    if (nrhs < 1) return fail(FIO_EINVAL, "nrhs must be >= 1 (got %d)", nrhs);
+    if (dtype != plan->dtype)
+        return fail(FIO_EINVAL, "dtype %d does not match the plan's dtype %d (%s)", dtype, plan->dtype,
+                    plan->dtype == FIO_C64 ? "FIO_C64" : "FIO_C128");
+    const size_t bytes = (size_t)nrhs * plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
+    if (overlaps(in, bytes, out, bytes)) return fail(FIO_EINVAL, "%s must not overlap", names);
+    return FIO_OK;
+}
+
 int set_device(fio_plan_t plan) {
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
@@ -601,8 +623,14 @@ int fio_apply_dphase(fio_plan_t plan, const void *f, void *u, void *du_da1, void
     if (!f || !du_da1 || !du_da2) return fail(FIO_EINVAL, "f, du_da1 and du_da2 must be non-NULL device pointers");
     if (nrhs < 1) return fail(FIO_EINVAL, "nrhs must be >= 1 (got %d)", nrhs);
     if (!tangent_supported_q(plan->q)) return fail(FIO_EINVAL, "phase derivatives need q <= 12 (got %d)", plan->q);
-    if (f == u || f == du_da1 || f == du_da2 || du_da1 == du_da2 || (u && (u == du_da1 || u == du_da2)))
-        return fail(FIO_EINVAL, "f, u, du_da1 and du_da2 must not overlap");
+    {
+        const size_t nb = (size_t)nrhs * plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
+        const void *arr[4] = {f, du_da1, du_da2, u};
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j)
+                if (arr[i] && arr[j] && overlaps(arr[i], nb, arr[j], nb))
+                    return fail(FIO_EINVAL, "f, u, du_da1 and du_da2 must not overlap");
+    }
     if ((rc = set_device(plan))) return rc;
     if (plan->nrhs_max < 3 && !plan->t0) {
         size_t tot = plan->total_bytes;
@@ -654,7 +682,12 @@ static int amp_args(fio_plan_t plan, const void *in, const void *g, const void *
     if (rc) return rc;
     if (!in || !g || !h || !out) return fail(FIO_EINVAL, "all array arguments must be non-NULL device pointers");
     if (rank < 1 || rank > 4096) return fail(FIO_EINVAL, "rank must be in [1, 4096] (got %d)", rank);
-    if (in == out || g == out || h == out) return fail(FIO_EINVAL, "the output must not overlap the inputs");
+    {
+        const size_t plane = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
+        if (overlaps(in, plane, out, plane) || overlaps(g, rank * plane, out, plane) ||
+            overlaps(h, rank * plane, out, plane))
+            return fail(FIO_EINVAL, "the output must not overlap the inputs");
+    }
     if ((rc = set_device(plan))) return rc;
     return ensure_amp(plan, rank);
 }
@@ -698,13 +731,10 @@ int fio_apply_amplitude_adjoint(fio_plan_t plan, const void *u, const void *g, c
     return FIO_OK;
 }
 
-int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream) {
+int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, int dtype, void *stream) {
     g_last_error.clear();
-    int rc = check_plan(plan);
+    int rc = check_apply_args(plan, f, u, nrhs, dtype, "f and u");
     if (rc) return rc;
-    if (!f || !u) return fail(FIO_EINVAL, "f and u must be non-NULL device pointers");
-    if (nrhs < 1) return fail(FIO_EINVAL, "nrhs must be >= 1 (got %d)", nrhs);
-    if (f == u) return fail(FIO_EINVAL, "f and u must not overlap");
     if ((rc = set_device(plan))) return rc;
     const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
     hipStream_t st = (hipStream_t)stream;
@@ -716,13 +746,10 @@ int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, void *stream) {
     return FIO_OK;
 }
 
-int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, void *stream) {
+int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, int dtype, void *stream) {
     g_last_error.clear();
-    int rc = check_plan(plan);
+    int rc = check_apply_args(plan, u, f, nrhs, dtype, "u and f");
     if (rc) return rc;
-    if (!f || !u) return fail(FIO_EINVAL, "u and f must be non-NULL device pointers");
-    if (nrhs < 1) return fail(FIO_EINVAL, "nrhs must be >= 1 (got %d)", nrhs);
-    if (f == u) return fail(FIO_EINVAL, "u and f must not overlap");
     if ((rc = set_device(plan))) return rc;
     const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
     hipStream_t st = (hipStream_t)stream;

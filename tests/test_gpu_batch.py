@@ -161,5 +161,8 @@ def test_batch_bad_arguments():
     f = _dev(white_noise(16, 1), torch.complex64)
     with pytest.raises(ValueError):
         batch.apply([f, f])
-    with pytest.raises(RuntimeError):
-        batch.apply([f], outs=[f])  # output aliases the input
+    with pytest.raises(ValueError):
+        batch.apply([f], outs=[f])  # output aliases the input: the binding refuses it
+    a = (ctypes.c_void_p * 1)(f.data_ptr())
+    assert lib.fio_batch_apply(batch._h, a, a, None) == -1          # and so does the library
+    assert lib.fio_batch_apply_adjoint(batch._h, a, a, None) == -1

@@ -367,6 +367,36 @@ def test_full_size_batched_parity_in_the_benchmark_configuration():
     assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
 
 
+def test_full_size_batched_adjoint_parity_in_the_benchmark_configuration():
+    """The batched adjoint in the benchmark's configuration (N = 1024, q = 9,
+    eq:ex1, complex64, 64 right-hand sides: the wide termination^H, the
+    adjoint levels, the matrix-core switch^H and initialisation^H) against
+    the oracle's adjoint restricted to three sampled source boxes at level
+    L - s of T_P, element by element at every source inside them, for the
+    first and the last right-hand side."""
+    import paper_0809_0719_amd as fio
+    from oracle.butterfly import box_of
+    N, q, R = 1024, 9, 64
+    v = white_noise(N, 4, nrhs=R)
+    plan = fio.Plan(N, q, fio.Phase(), dtype=torch.complex64, nrhs_max=R)
+    print(f"adjoint N={N} q={q} nrhs={R}", flush=True)
+    g = plan.adjoint(_dev(v, torch.complex64))
+    model = ButterflyModel(N, q, D.Phase())
+    lB = model.L - model.s
+    b1, b2 = box_of(model.p1, lB), box_of(model.p2, lB)
+    pick = np.random.default_rng(78).choice(N * N, 3, replace=False)   # boxes of three sampled sources
+    sources = sorted({(int(b1[j]), int(b2[j])) for j in pick})
+    mask = np.zeros(N * N, dtype=bool)
+    for c1, c2 in sources:
+        mask |= (b1 == c1) & (b2 == c2)
+    for r in (0, R - 1):
+        f_ref = model.adjoint(v[r], sources=sources).ravel()[mask]
+        got = g[r].cpu().numpy().ravel()[mask]
+        e, em = rel_l2(got, f_ref), rel_max(got, f_ref)
+        print(f"batched adjoint full size, rhs {r}, {mask.sum()} sources: rel l2 {e:.2e}, rel max {em:.2e}")
+        assert e <= FP32_TOL and em <= 4 * FP32_TOL
+
+
 @pytest.mark.parametrize("nr", [33, 65])
 @pytest.mark.parametrize("q", [3, 4, 5, 6, 7, 8, 9])
 def test_matrix_core_switch(q, nr):

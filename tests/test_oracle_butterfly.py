@@ -126,3 +126,70 @@ def test_restricted_targets_equal_the_full_pass():
     for key, part in lev_part.items():
         for (a1, a2), w in part.items():
             assert np.array_equal(w, lev_full[key][a1, a2])
+
+
+def test_restricted_sources_equal_the_full_adjoint():
+    # the adjoint computed only over the ancestors of some source boxes gives
+    # the same values at the sources inside those boxes, zero elsewhere, for
+    # every s from 0 to 3 (each level kind present at least once)
+    from oracle.butterfly import box_of
+    for N, q, s in ((16, 4, 0), (32, 4, 1), (64, 5, 2), (64, 5, 3), (256, 4, 3)):
+        m = ButterflyModel(N, q, D.Phase(a1=1.05, a2=0.9), s=s)
+        u = white_noise(N, 4)
+        full = m.adjoint(u).ravel()
+        lB = m.L - m.s
+        nb = 1 << lB
+        rng = np.random.default_rng(N + s)
+        src = [tuple(int(v) for v in rng.integers(0, nb, 2)) for _ in range(3)] + [(0, 0), (nb - 1, nb - 1)]
+        part = m.adjoint(u, sources=src).ravel()
+        b1, b2 = box_of(m.p1, lB), box_of(m.p2, lB)
+        mask = np.zeros(N * N, dtype=bool)
+        for c1, c2 in src:
+            mask |= (b1 == c1) & (b2 == c2)
+        assert mask.any()
+        assert np.abs(part[mask] - full[mask]).max() <= 1e-13 * np.abs(full[mask]).max(), (N, q, s)
+        assert not np.any(part[~mask])
+
+
+def _err_s3(q, model=ButterflyModel):
+    """eq:err of the step model at the benchmark's schedule depth: N = 256,
+    s = 3 (recursion from level L-3 of T_P to level 3, as the numerical
+    section runs it), lm = 4 -- initialisation, one p-level, the switch, one
+    x-level and the termination over 4^3 boxes B -- with the Fourier phase,
+    on two target boxes (128 points) against the direct sum there."""
+    N = 256
+    f = white_noise(N, 1)
+    side = 8
+    targets = [(1, 2), (31, 5)]
+    rows = np.array([(a1 * side + i) * N + a2 * side + j for a1, a2 in targets
+                     for i in range(side) for j in range(side)])
+    m = model(N, q, FOURIER)
+    assert (m.s, m.lm) == (3, 4)
+    u = m.apply(f, targets=targets)
+    return D.rel_err(D.forward(N, FOURIER, f, rows), u.ravel()[rows])
+
+
+def test_spectral_convergence_at_s3():
+    # 2^s = 8 termination grid columns and 64 boxes B: a slip that confuses
+    # 2^s with 2s or 4^s with 2^s is invisible at s = 1, 2 and O(1) here
+    errs = [_err_s3(q) for q in (9, 13, 17, 21)]
+    assert all(b < a / 30 for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-8, errs
+
+
+class _TermGrid2s(ButterflyModel):
+    """Termination interpolating at j/(2s) - 1/2 instead of j/2^s - 1/2: the
+    same points at s = 1 and s = 2."""
+    def term_interp(self):
+        from oracle.butterfly import lagrange
+        xi = np.arange(1 << self.s) / (2 * self.s) - 0.5
+        return lagrange(xi, self.z)
+
+
+def test_planted_mistake_visible_only_at_s3():
+    for s in (1, 2):
+        good = _err(32, 9, FOURIER, s=s)
+        assert _err(32, 9, FOURIER, s=s, model=_TermGrid2s) == good
+    good, bad = _err_s3(13), _err_s3(13, model=_TermGrid2s)
+    assert good < 1e-3
+    assert bad > 100 * good, (good, bad)
