@@ -217,6 +217,28 @@ int fio_apply_amplitude(fio_plan_t plan, const void *f, const void *g, const voi
 int fio_apply_amplitude_adjoint(fio_plan_t plan, const void *u, const void *g, const void *h, int rank,
                                 void *f, void *stream);
 
+/* fio_apply_amplitude for callers that cannot allocate device memory during
+ * the call -- code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc: the same computation with the same kernels, but its
+ * two staging buffers (the rank scaled inputs h_t . f and the rank butterfly
+ * outputs) live in a static device array of 64 MiB that the library holds
+ * on every device it is loaded on, instead of the plan's workspace, which
+ * fio_apply_amplitude allocates on first use and regrows (after a device
+ * synchronisation) for a larger rank.  This call allocates nothing, frees
+ * nothing and synchronises nothing.
+ *   Limit: 2 rank N^2 complex values of the plan dtype must fit in 64 MiB
+ *   (complex64: rank N^2 <= 4194304, e.g. rank 64 at N = 256, 4 at N = 1024);
+ *   larger requests return FIO_EINVAL before any launch.
+ *   Every call on one device shares that device's array and leaves the last
+ *   call's values in it (each call fully overwrites what it reads, nothing
+ *   needs to start at zero): calls that may overlap in time on one device --
+ *   on different streams, or from different threads -- race; serialise them
+ *   (e.g. on one stream).  The plan's own weight buffers are used as by
+ *   fio_apply.
+ *   Arguments, layouts and errors otherwise as fio_apply_amplitude. */
+int fio_apply_amplitude_noalloc(fio_plan_t plan, const void *f, const void *g, const void *h, int rank, void *u,
+                                void *stream);
+
 /* ---- uneven batches ------------------------------------------------------
  * A batch applies several plans (any N, q, phase, dtype) as one unit, the
  * mixed-size workload of many small and large problems: fio_batch_apply

@@ -47,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "fio_plan", "fio_plan_ex", "fio_set_phase", "fio_plan_get_info", "fio_apply",
     "fio_apply_adjoint", "fio_debug_stage", "fio_destroy", "fio_last_error",
     "fio_profile_enable", "fio_profile_read", "fio_apply_dphase", "fio_apply_amplitude",
-    "fio_apply_amplitude_adjoint", "fio_batch_create", "fio_batch_apply", "fio_batch_apply_adjoint",
+    "fio_apply_amplitude_adjoint", "fio_apply_amplitude_noalloc", "fio_batch_create", "fio_batch_apply", "fio_batch_apply_adjoint",
     "fio_batch_destroy", "fio_direct_rows", "fio_select_q", "fio3_plan", "fio3_apply", "fio3_apply_adjoint",
     "fio3_destroy",
 )
@@ -113,6 +113,7 @@ def load_library():
     lib.fio_apply_dphase.argtypes = [vp, vp, vp, vp, vp, i, vp]
     lib.fio_apply_amplitude.argtypes = [vp, vp, vp, vp, i, vp, vp]
     lib.fio_apply_amplitude_adjoint.argtypes = [vp, vp, vp, vp, i, vp, vp]
+    lib.fio_apply_amplitude_noalloc.argtypes = [vp, vp, vp, vp, i, vp, vp]
     lib.fio_debug_stage.argtypes = [vp, vp, i, vp, vp]
     lib.fio_batch_create.argtypes = [ctypes.POINTER(vp), i, i, ctypes.POINTER(vp)]
     lib.fio_batch_apply.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]

@@ -180,6 +180,14 @@ hipError_t launch_step3_adj(int dtype, int step, const Geom3 &g, const Tab3 &tb,
 int set_error(int code, const char *fmt, ...);
 int set_hip_error(hipError_t e, const char *what);
 void clear_error();
+// fio_apply_amplitude with its two staging buffers (2 rank N^2 complex
+// values) taken from a caller-provided device array instead of the plan's
+// workspace: scratch_of_device(d) returns the array's address on device d
+// (NULL after setting the error message on failure); FIO_EINVAL when the
+// staging needs more than scratch_bytes.  Allocates nothing.
+int amplitude_apply_in(fio_plan_t plan, const void *f, const void *g, const void *h, int rank, void *u,
+                       size_t scratch_bytes, void *(*scratch_of_device)(int device), void *stream);
+
 struct PlanView {
     int N, q, dtype, device;
     PhaseDev ph;

@@ -5,6 +5,8 @@
 // plain streaming kernels (bandwidth-bound).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fio_kernels_common.h"
 
 namespace fio {
@@ -70,4 +72,43 @@ hipError_t launch_combine_planes(int dtype, bool conj, const void *a, const void
                              : amp_t<float>(true, conj, a, b, out, n, rank, st);
 }
 
+// ---------------------------------------------------------------------------
+// Staging of the allocation-free amplitude apply: a file-scope device array
+// (each device that loads the library holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel -- on the host
+// that name is only a stand-in -- but the address hipGetSymbolAddress gives
+// for it on each device, looked up once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+
+// Address of `scratch` on `device` (which must be current); NULL on failure.
+static void *scratch_of_device(int device) {
+    if (device < 0 || device >= MAX_DEVICES) {
+        set_error(FIO_EDEVICE, "device %d beyond the %d devices the scratch table covers", device, MAX_DEVICES);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+            return nullptr;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
 }  // namespace fio
+
+extern "C" int fio_apply_amplitude_noalloc(fio_plan_t plan, const void *f, const void *g, const void *h, int rank,
+                                           void *u, void *stream) {
+    return fio::amplitude_apply_in(plan, f, g, h, rank, u, fio::NOALLOC_SCRATCH_BYTES, fio::scratch_of_device,
+                                   stream);
+}

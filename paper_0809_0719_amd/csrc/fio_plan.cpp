@@ -688,47 +688,69 @@ static int amp_args(fio_plan_t plan, const void *in, const void *g, const void *
             overlaps(h, rank * plane, out, plane))
             return fail(FIO_EINVAL, "the output must not overlap the inputs");
     }
-    if ((rc = set_device(plan))) return rc;
-    return ensure_amp(plan, rank);
+    return set_device(plan);
 }
+
+// The separated-amplitude pass with its two staging buffers given: buf0
+// receives the rank scaled inputs, buf1 the rank butterfly outputs (rank
+// planes of N^2 complex values each).
+static int amp_run(fio_plan_t plan, bool adjoint, const void *in, const void *g, const void *h, int rank, void *out,
+                   void *buf0, void *buf1, hipStream_t st) {
+    const size_t n2 = (size_t)plan->N * plan->N, step = n2 * (plan->dtype == FIO_C128 ? 16 : 8);
+    // forward: buf0 = h_t . f, buf1 = B buf0, u = sum_t g_t . buf1;
+    // adjoint: buf0 = conj(g_t) . u, buf1 = B^H buf0, f = sum_t conj(h_t) . buf1
+    hipError_t e = launch_scale_planes(plan->dtype, adjoint, adjoint ? g : h, in, buf0, n2, rank, st);
+    if (e != hipSuccess) return hip_fail(e, "amplitude scale launch");
+    for (int r = 0; r < rank; r += plan->nrhs_max) {
+        const int nr = std::min(plan->nrhs_max, rank - r);
+        const int rc = adjoint ? run_adjoint(plan, (const char *)buf0 + r * step, (char *)buf1 + r * step, nr, st)
+                               : run_forward(plan, (const char *)buf0 + r * step, (char *)buf1 + r * step, nr, -1,
+                                             nullptr, st);
+        if (rc) return rc;
+    }
+    e = launch_combine_planes(plan->dtype, adjoint, adjoint ? h : g, buf1, out, n2, rank, st);
+    if (e != hipSuccess) return hip_fail(e, "amplitude combine launch");
+    return FIO_OK;
+}
+
+}  // extern "C"
+
+namespace fio {
+
+int amplitude_apply_in(fio_plan_t plan, const void *f, const void *g, const void *h, int rank, void *u,
+                       size_t scratch_bytes, void *(*scratch_of_device)(int device), void *stream) {
+    g_last_error.clear();
+    int rc = amp_args(plan, f, g, h, rank, u);
+    if (rc) return rc;
+    const size_t need = 2 * (size_t)rank * plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
+    if (need > scratch_bytes)
+        return fail(FIO_EINVAL,
+                    "rank %d at N = %d needs %zu bytes of staging, more than the %zu bytes of the static scratch "
+                    "array (at most 2 rank N^2 complex values)",
+                    rank, plan->N, need, scratch_bytes);
+    char *base = (char *)scratch_of_device(plan->device);
+    if (!base) return FIO_EDEVICE;  // the message is set by scratch_of_device
+    return amp_run(plan, false, f, g, h, rank, u, base, base + need / 2, (hipStream_t)stream);
+}
+
+}  // namespace fio
+
+extern "C" {
 
 int fio_apply_amplitude(fio_plan_t plan, const void *f, const void *g, const void *h, int rank, void *u,
                         void *stream) {
     g_last_error.clear();
     int rc = amp_args(plan, f, g, h, rank, u);
-    if (rc) return rc;
-    const size_t n2 = (size_t)plan->N * plan->N, step = n2 * (plan->dtype == FIO_C128 ? 16 : 8);
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_scale_planes(plan->dtype, false, h, f, plan->amp0, n2, rank, st);
-    if (e != hipSuccess) return hip_fail(e, "amplitude scale launch");
-    for (int r = 0; r < rank; r += plan->nrhs_max) {
-        const int nr = std::min(plan->nrhs_max, rank - r);
-        rc = run_forward(plan, (const char *)plan->amp0 + r * step, (char *)plan->amp1 + r * step, nr, -1,
-                         nullptr, st);
-        if (rc) return rc;
-    }
-    e = launch_combine_planes(plan->dtype, false, g, plan->amp1, u, n2, rank, st);
-    if (e != hipSuccess) return hip_fail(e, "amplitude combine launch");
-    return FIO_OK;
+    if (rc || (rc = ensure_amp(plan, rank))) return rc;
+    return amp_run(plan, false, f, g, h, rank, u, plan->amp0, plan->amp1, (hipStream_t)stream);
 }
 
 int fio_apply_amplitude_adjoint(fio_plan_t plan, const void *u, const void *g, const void *h, int rank, void *f,
                                 void *stream) {
     g_last_error.clear();
     int rc = amp_args(plan, u, g, h, rank, f);
-    if (rc) return rc;
-    const size_t n2 = (size_t)plan->N * plan->N, step = n2 * (plan->dtype == FIO_C128 ? 16 : 8);
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_scale_planes(plan->dtype, true, g, u, plan->amp0, n2, rank, st);
-    if (e != hipSuccess) return hip_fail(e, "amplitude scale launch");
-    for (int r = 0; r < rank; r += plan->nrhs_max) {
-        const int nr = std::min(plan->nrhs_max, rank - r);
-        rc = run_adjoint(plan, (const char *)plan->amp0 + r * step, (char *)plan->amp1 + r * step, nr, st);
-        if (rc) return rc;
-    }
-    e = launch_combine_planes(plan->dtype, true, h, plan->amp1, f, n2, rank, st);
-    if (e != hipSuccess) return hip_fail(e, "amplitude combine launch");
-    return FIO_OK;
+    if (rc || (rc = ensure_amp(plan, rank))) return rc;
+    return amp_run(plan, true, u, g, h, rank, f, plan->amp0, plan->amp1, (hipStream_t)stream);
 }
 
 int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, int dtype, void *stream) {
