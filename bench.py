@@ -81,7 +81,8 @@ def algorithmic_work(kind: str, N: int, q: int, s: int, nrhs: int):
     raise ValueError(kind)
 
 
-def roofline_of(kind: str, avg_ms: float, launches: int, N: int, q: int, s: int, nrhs: int) -> dict:
+def roofline_of(kind: str, avg_ms: float, launches: int, N: int, q: int, s: int, nrhs: int,
+                contract: str = "fp") -> dict:
     """Both bounds of one kernel kind: achieved GB/s against the HBM peak and
     achieved TFLOP/s against the FP32 peak; the binding one is the larger
     fraction (the bound the kernel is closest to)."""
@@ -95,13 +96,24 @@ def roofline_of(kind: str, avg_ms: float, launches: int, N: int, q: int, s: int,
     if hf >= ff:
         out.update(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hf)
     else:
-        out.update(bound="mfma" if kind in MFMA_KINDS else "alu", achieved=tfs, peak=FP32_PEAK_TFLOPS,
+        out.update(bound="mfma" if kind in mfma_kinds(q, s, nrhs, contract) else "alu", achieved=tfs, peak=FP32_PEAK_TFLOPS,
                    unit="TFLOP/s", frac=ff)
     return out
 
 
-# kernel kinds that run on the matrix cores in the benchmark's configuration
-MFMA_KINDS = ("init", "init_adj", "switch", "switch_adj")
+def mfma_kinds(q: int, s: int, nrhs: int, contract: str = "fp") -> tuple:
+    """Kernel kinds the library runs as FP32 matrix-core products for a
+    complex64 plan: the initialisations at s = 3, q <= 9; the switches for
+    chunks of 32 or more right-hand sides at q <= 9; with contract "mfma" also
+    the p-levels and adjoint x-levels of such chunks."""
+    kinds = []
+    if s == 3 and 3 <= q <= 9:
+        kinds += ["init", "init_adj"]
+    if 3 <= q <= 9 and nrhs >= 32:
+        kinds += ["switch", "switch_adj"]
+        if contract == "mfma":
+            kinds += ["plevel", "xlevel_adj"]
+    return tuple(kinds)
 
 
 def traffic_from_profiles(kernel: str, config: dict):
@@ -300,8 +312,9 @@ def main():
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--q", type=int, default=9)
     ap.add_argument("--nrhs", type=int, default=64)
-    ap.add_argument("--contract", choices=["fp", "bf16"], default="fp",
-                    help="interpolation contractions: FP32 vector ALUs or BF16 MFMA (FP32 accumulation)")
+    ap.add_argument("--contract", choices=["fp", "mfma", "bf16"], default="fp",
+                    help="level contractions: FP32 vector ALUs, FP32 matrix cores, or BF16 matrix cores "
+                         "(FP32 accumulation)")
     ap.add_argument("--rows", type=int, default=256, help="sampled points for eq:err (the paper's S)")
     ap.add_argument("--cpu-rows", type=int, default=3072,
                     help="sampled points of the CPU baseline (about 10 s of the FP64 direct sum)")
@@ -395,7 +408,7 @@ def main():
         # levels and switches take the whole chunk per launch; the
         # initialisation and termination may take one right-hand side each
         nr = R * args.steps / k_n if kind in ("init", "init_adj", "term", "term_adj") else R
-        per_kind[kind] = roofline_of(kind, k_ms / k_n, k_n, N, q, plan.s, nr)
+        per_kind[kind] = roofline_of(kind, k_ms / k_n, k_n, N, q, plan.s, nr, args.contract)
     kind = max(per_kind, key=lambda k: prof[k][0])
     kk = per_kind[kind]
     roof = {"bound": kk["bound"], "kernel": f"k_{kind}", "achieved": kk["achieved"], "peak": kk["peak"],

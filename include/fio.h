@@ -92,6 +92,14 @@ typedef struct {
  *                    Requires q <= 12.                                     */
 #define FIO_CONTRACT_FP   0
 #define FIO_CONTRACT_BF16 1
+/* FIO_CONTRACT_MFMA: the p-levels and the adjoint x-levels of chunks of 32 or
+ *                    more right-hand sides run their interpolation passes as
+ *                    FP32 matrix-core products (v_mfma_f32_4x4x1f32) with
+ *                    the Chebyshev-symmetric halves of the interpolation
+ *                    matrices; every other step as FIO_CONTRACT_FP.  Results
+ *                    agree with FIO_CONTRACT_FP to FP32 rounding.  Requires
+ *                    FIO_C64 and q <= 9.                                     */
+#define FIO_CONTRACT_MFMA 2
 
 typedef struct fio_plan_s *fio_plan_t;
 
@@ -109,7 +117,8 @@ typedef struct {
                      take nrhs in chunks of nrhs_max, computing every kernel
                      value of the levels and the switch once per chunk (the
                      vectorised butterfly of Sec. 4, last paragraphs)        */
-    int contract; /* FIO_CONTRACT_FP (default) or FIO_CONTRACT_BF16           */
+    int contract; /* FIO_CONTRACT_FP (default), FIO_CONTRACT_BF16 or
+                     FIO_CONTRACT_MFMA                                        */
 } fio_plan_opts_t;
 
 /* Geometry and sizes of a plan. */

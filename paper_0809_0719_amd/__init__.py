@@ -38,6 +38,7 @@ C128 = 0
 C64 = 1
 CONTRACT_FP = 0
 CONTRACT_BF16 = 1
+CONTRACT_MFMA = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfio.so")
@@ -159,7 +160,9 @@ class Plan:
     the switch (the plan holds 2 x nrhs_max x N^2 q^2 complex weights);
     contract: "fp" (contractions in the weight precision on the vector ALUs)
     or "bf16" (BF16 operands, FP32 accumulation on the matrix cores;
-    complex64 plans, q <= 12).
+    complex64 plans, q <= 12) or "mfma" (FP32 matrix-core p-levels and
+    adjoint x-levels for chunks of 32 or more right-hand sides, the rest as
+    "fp"; complex64 plans, q <= 9).
     """
 
     def __init__(self, N: int, q: int, phase: Phase = Phase(), s: int | None = None,
@@ -170,11 +173,11 @@ class Plan:
             raise ValueError("dtype must be torch.complex64 or torch.complex128")
         self.dtype = dtype
         self.device = torch.device("cuda", torch.cuda.current_device())
-        if contract not in ("fp", "bf16"):
-            raise ValueError('contract must be "fp" or "bf16"')
+        codes = {"fp": CONTRACT_FP, "bf16": CONTRACT_BF16, "mfma": CONTRACT_MFMA}
+        if contract not in codes:
+            raise ValueError('contract must be "fp", "bf16" or "mfma"')
         opts = _COpts(-1 if s is None else int(s), -1 if lm is None else int(lm),
-                      C64 if dtype == torch.complex64 else C128, int(nrhs_max),
-                      CONTRACT_BF16 if contract == "bf16" else CONTRACT_FP)
+                      C64 if dtype == torch.complex64 else C128, int(nrhs_max), codes[contract])
         h = ctypes.c_void_p()
         _check(lib.fio_plan_ex(int(N), int(q), ctypes.byref(_cphase(phase)), ctypes.byref(opts),
                                ctypes.byref(h)), "fio_plan_ex")

@@ -15,7 +15,7 @@ SOURCES = ["fio_plan.cpp", "fio_kernels_fwd.hip", "fio_kernels_adj.hip", "fio_ke
            "fio_kernels_mfma.hip",
            "fio_kernels_tan.hip", "fio_kernels_amp.hip",
            "fio_kernels_direct.hip", "fio_batch.cpp", "fio_kernels_swadj.hip",
-           "fio_kernels_3d.hip", "fio3.cpp"]
+           "fio_kernels_3d.hip", "fio3.cpp", "fio_kernels_lvlmm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

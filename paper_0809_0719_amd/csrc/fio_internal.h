@@ -103,6 +103,15 @@ bool switch_adj_mfma_supported(int q, int nrhs);
 hipError_t launch_switch_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs,
                                   size_t plane, hipStream_t st);
 
+// Levels on the matrix cores (fio_kernels_lvlmm.hip, complex64, q <= 9): the
+// p-level (adjoint_x false; eq:alg2b, level l from level l - 1) or the
+// adjoint x-level (adjoint_x true; the transpose of eq:alg2c at level l, from
+// level l to level l - 1), `nrhs` right-hand sides whose weights are planes
+// `plane` complex values apart.
+bool level_mfma_supported(int q);
+hipError_t launch_level_mm(bool adjoint_x, const Geom &g, const PhaseDev &ph, const Tables &tb, int level,
+                           const void *w_in, void *w_out, int nrhs, size_t plane, hipStream_t st);
+
 // Termination and its adjoint for `nrhs` > 1 right-hand sides in one launch
 // (fio_kernels_term.hip): weights planes `plane` apart, potentials `uplane`.
 hipError_t launch_term_batch(int dtype, const Geom &g, const PhaseDev &ph, const Tables &tb, const void *w_in,

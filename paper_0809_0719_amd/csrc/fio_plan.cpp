@@ -142,6 +142,10 @@ int dmalloc(void **ptr, size_t bytes, size_t *total, const char *what) {
     return FIO_OK;
 }
 
+// With FIO_CONTRACT_MFMA, chunks of at least this many right-hand sides take
+// the p-levels and the adjoint x-levels on the matrix cores.
+constexpr int LVL_MM_MIN_RHS = 32;
+
 int check_plan(fio_plan_t plan) {
     if (!plan) return fail(FIO_EINVAL, "plan is NULL");
     return FIO_OK;
@@ -268,8 +272,10 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     if (s < 0 || s > 3) return fail(FIO_EINVAL, "s must be in [0, 3] (got %d)", s);
     if (!(s <= lm && lm <= L - s)) return fail(FIO_EINVAL, "need s <= lm <= L - s (s=%d, lm=%d, L=%d)", s, lm, L);
     if (dtype != FIO_C64 && dtype != FIO_C128) return fail(FIO_EINVAL, "unknown dtype %d", dtype);
-    if (contract != FIO_CONTRACT_FP && contract != FIO_CONTRACT_BF16)
+    if (contract != FIO_CONTRACT_FP && contract != FIO_CONTRACT_BF16 && contract != FIO_CONTRACT_MFMA)
         return fail(FIO_EINVAL, "unknown contraction precision %d", contract);
+    if (contract == FIO_CONTRACT_MFMA && (dtype != FIO_C64 || !level_mfma_supported(q)))
+        return fail(FIO_EINVAL, "FP32 matrix-core levels need dtype FIO_C64 and q <= 9 (dtype %d, q %d)", dtype, q);
     if (contract == FIO_CONTRACT_BF16 && (dtype != FIO_C64 || !mfma_supported_q(q)))
         return fail(FIO_EINVAL, "BF16 contractions need dtype FIO_C64 and q <= 12 (dtype %d, q %d)", dtype, q);
 
@@ -446,6 +452,9 @@ int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info) {
     return FIO_OK;
 }
 
+// Whether a chunk of nr right-hand sides takes the matrix-core levels.
+static bool level_mm(fio_plan_t p, int nr) { return p->contract == FIO_CONTRACT_MFMA && nr >= LVL_MM_MIN_RHS; }
+
 // The kernel-value table of the matrix-core initialisation, remade after a
 // phase change (on the stream of the call that needs it).
 static hipError_t ensure_etab(fio_plan_t p, const PhaseDev &ph, const Sources &src, hipStream_t st) {
@@ -492,7 +501,8 @@ static int run_forward(fio_plan_t p, const void *f, void *u, int nr, int last_st
             Timed tm(p, FIO_K_PLEVEL, st);
             e = p->contract == FIO_CONTRACT_BF16
                     ? launch_plevel_mfma(p->geom, ph, p->tb, l, a, b, nr, p->plane, st)
-                    : launch_plevel(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
+                : level_mm(p, nr) ? launch_level_mm(false, p->geom, ph, p->tb, l, a, b, nr, p->plane, st)
+                                  : launch_plevel(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
         }
         if (e != hipSuccess) return hip_fail(e, "p-level launch");
         std::swap(a, b);
@@ -554,7 +564,8 @@ static int run_adjoint(fio_plan_t p, const void *u, void *f, int nr, hipStream_t
     for (int l = p->L - p->s; l >= p->lm + 1; --l) {
         {
             Timed tm(p, FIO_K_XLEVEL_ADJ, st);
-            e = launch_xlevel_adj(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
+            e = level_mm(p, nr) ? launch_level_mm(true, p->geom, ph, p->tb, l, a, b, nr, p->plane, st)
+                                : launch_xlevel_adj(p->dtype, p->geom, ph, p->tb, l, a, b, nr, p->plane, st);
         }
         if (e != hipSuccess) return hip_fail(e, "x-level^H launch");
         std::swap(a, b);

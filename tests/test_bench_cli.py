@@ -16,10 +16,19 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in p.stderr
 
 
-def test_switch_pricing_follows_the_dispatch_rule():
+def test_kernel_pricing_follows_the_dispatch_rule():
     import bench
-    # complex64 batches of >= 32 right-hand sides at q <= 9 run on the matrix cores
-    assert bench.switch_on_mfma(9, 64) and bench.switch_on_mfma(3, 32)
-    assert not bench.switch_on_mfma(9, 31) and not bench.switch_on_mfma(10, 64)
-    # 4 q^4 N^2 flops per right-hand side: q = 9, N = 1024
-    assert bench.mfma_switch_flops(1024, 9) == 4.0 * 9 ** 4 * 1024 ** 2
+    # complex64 chunks of >= 32 right-hand sides at q <= 9: switches on the matrix cores
+    assert {"switch", "switch_adj"} <= set(bench.mfma_kinds(9, 3, 64))
+    assert {"switch", "switch_adj"} <= set(bench.mfma_kinds(3, 3, 32))
+    assert "switch" not in bench.mfma_kinds(9, 3, 31) and not bench.mfma_kinds(10, 3, 64)
+    # initialisation on the matrix cores only at s = 3
+    assert "init" in bench.mfma_kinds(9, 3, 1) and "init" not in bench.mfma_kinds(9, 2, 64)
+    # levels only with contract "mfma"
+    assert "plevel" not in bench.mfma_kinds(9, 3, 64)
+    assert {"plevel", "xlevel_adj"} <= set(bench.mfma_kinds(9, 3, 64, "mfma"))
+    # switch: 4 q^4 N^2 flops per right-hand side (q = 9, N = 1024), both halves of the weights read and written
+    nbytes, flops = bench.algorithmic_work("switch", 1024, 9, 3, 1)
+    assert flops == 4.0 * 9 ** 4 * 1024 ** 2 and nbytes == 2 * 1024 ** 2 * 81 * 8
+    r = bench.roofline_of("switch", 1.0, 1, 1024, 9, 3, 64)
+    assert r["bound"] in ("hbm", "mfma") and abs(r["frac"] - max(r["hbm_frac"], r["fp32_frac"])) < 1e-12
