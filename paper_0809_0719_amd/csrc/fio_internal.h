@@ -43,6 +43,15 @@ struct Tables {
     const float  *Mf;   // FP32 copy
     const double *Tt;
     const float  *Ttf;
+    // Chebyshev-symmetric halves of M_0 (M_1 = J M_0 J, J the reversal), four
+    // q x q matrices: [0] S[n][m] = (M_0[n][m] + M_0[q-1-n][m]) / 2 and
+    // [1] A[n][m] = (M_0[n][m] - M_0[q-1-n][m]) / 2 for contractions that sum
+    // two children into one output; [2] ST[n][m] = (M_0[m][n] + M_0[q-1-m][n]) / 2
+    // and [3] AT[n][m] = (M_0[m][n] - M_0[q-1-m][n]) / 2 for m < q/2
+    // (ST[n][(q-1)/2] = M_0[(q-1)/2][n] for odd q, zero past) for contractions
+    // that feed one input to two children.
+    const double *SA;   // FP64
+    const float  *SAf;  // FP32
 };
 
 // Sources of T_P sorted by their box at level L-s (a CSR over Morton order).

@@ -94,20 +94,16 @@ __global__ __launch_bounds__(NT) void k_term_adj(Geom g, PhaseDev ph, Tables tb,
 // x-level^H at level l: from the outputs (A_j, B) back to the inputs (A_p, B_c)
 //   delta^{A_p B_c}_t' = E(x^{A_p}_t', p0(B_c)) sum_j sum_t M_j1[t'1][t1] M_j2[t'2][t2]
 //                          conj E(x^{A_j}_t, p0(B_c)) delta^{A_j B}_t
-// First pass: thread (j1, c2, t1, j2) forms row t1 of conj E delta for its
-// child (j1, j2) and both c1 and contracts over t2 with M_j2; the partial
-// rows of the two j2 are summed.  Second pass: thread (c, t'2, half)
-// contracts over t1 with M_j1, sums j1 and applies the factor
-// E(x^{A_p}_t', p0(B_c)).
-// SPLIT (FP32): j2 is the same for a pair of waves (threads [128 j2,
-// 128 j2 + 128)), so the first-pass factors are wave-uniform (SGPR
-// operands); both partial rows go to LDS and the second pass adds them.
-// Otherwise (FP64, whose doubled partial rows would not fit the LDS budget):
-// the two j2 of a row are adjacent lanes and add their rows through a DPP
-// lane exchange before one of them stores the sum.
-template <typename T, int Q>
-constexpr bool xadj_split() { return sizeof(T) == 4; }
-
+// Each 1-D pass sums two children j: with M_1 = J M_0 J,
+//   M_0 u + M_1 y = S (u + J y) + A (u - J y),
+// and rows n, q-1-n of S agree and of A differ in sign, so P = S_n . a and
+// D = A_n . b give outputs n (P + D) and q-1-n (P - D): q MACs per output
+// instead of 2q.  First pass: thread (j1, c, t1) takes row t1 of the two
+// children (j1, 0), (j1, 1), applies conj E(x^{A_j}_t, p0(B_c)) and
+// contracts over t2.  Second pass: thread (h, block, c, t'2) takes column
+// t'2 of the first-pass rows of both j1, produces the row pairs n = h,
+// h + 2, ... and applies E(x^{A_p}_t', p0(B_c)); h is the same for two
+// waves.  The factors S, A are the same for every thread (SGPR operands).
 template <typename T, int Q, bool HOIST>
 __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables tb, int level,
                                                    const cpx<T> *__restrict__ win,
@@ -115,15 +111,11 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
                                                    int nrhs, size_t plane) {
     constexpr int QQ = Q * Q;
     constexpr int TPB = 8 * Q;
-    constexpr bool SPLIT = xadj_split<T, Q>();
-    constexpr int NS = SPLIT ? 2 : 1;
-    constexpr int BPW = blocks_per_wg<T, Q, 8 * NS>();
-    constexpr int H1 = (Q + 1) / 2;
-    __shared__ T Ms[2][Q][Q];                       // Ms[a][t'][t] = M_a[t'][t]
-    // rows padded to q^2 + 9 for q = 9: an LDS bank model of both passes' access
-    // patterns (32 banks, 16 lanes per 64-bit access cycle) finds 22% fewer cycles
-    constexpr int YROW = QQ + (Q == 9 ? 9 : 0);
-    __shared__ cpx<T> Y[BPW][NS][2][4][YROW];       // [j2 partial][j1][c][t1][t'2]
+    constexpr int BPW = blocks_per_wg<T, Q, 8>();
+    static_assert(BPW * 4 * Q <= NT / 2, "second pass: a block's columns fit a half workgroup");
+    constexpr int H1 = (Q + 1) / 2, H = Q / 2;
+    constexpr int NK = (H1 + 1) / 2;                // row pairs per second-pass thread
+    __shared__ cpx<T> Y[BPW][2][4][QQ];             // [j1][c][t1][t'2]
     __shared__ double sp[BPW][2][Q], cp[BPW][2][Q];
     __shared__ double sj[BPW][2][2][Q], cj[BPW][2][2][Q];
     __shared__ double r0c[BPW][2], ct0[BPW][2], st0[BPW][2];
@@ -135,9 +127,8 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
     const int lB = g.L - level;
     const size_t nBl = (size_t)1 << (2 * lB);
     const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
+    cptr<T> SAg = to_constant(pick_SA<T>(tb));
 
-    const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) (&Ms[0][0][0])[i] = Mg[i];
     uint32_t mB = 0, mAp = 0;
     int b1 = 0, b2 = 0, ap1 = 0, ap2 = 0;
     if (active) {
@@ -167,171 +158,125 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
         }
     }
     lds_barrier();
-    // first-pass item (block fb, j1, c2f, t1, j2)
-    int fb, j1, c2f, t1, j2;
-    if constexpr (SPLIT) {
-        j2 = __builtin_amdgcn_readfirstlane(tid / (NT / 2));
-        const int fi = tid - j2 * (NT / 2);
-        fb = fi / (4 * Q);
-        const int fk = fi - fb * (4 * Q);
-        j1 = fk / (2 * Q);
-        c2f = (fk / Q) & 1;
-        t1 = fk % Q;
-    } else {
-        // rr = ((j1 * 2 + c2) * Q + t1) * 2 + j2: the two j2 of a row are adjacent lanes
-        fb = bbl;
-        j2 = rr & 1;
-        const int k1 = rr >> 1;
-        t1 = k1 % Q;
-        const int jc = k1 / Q;
-        c2f = jc & 1;
-        j1 = jc >> 1;
-    }
-    const size_t fblk = (size_t)blockIdx.x * BPW + fb;
-    const bool factive = fb < BPW && fblk < nblk;
-    uint32_t fmB = 0, fmAp = 0;
-    int fap1 = 0, fap2 = 0;
-    if (factive) {
-        fmB = (uint32_t)(fblk & (nBl - 1));
-        fmAp = (uint32_t)(fblk >> (2 * lB));
-        morton_decode(fmAp, fap1, fap2);
-    }
-    // second pass: thread (c, t'2, half) of its block
-    const int c = rr / (2 * Q), k2 = rr - c * 2 * Q;
-    const int h = k2 / Q, tp2 = k2 - h * Q;
-    const int c1 = c >> 1, c2 = c & 1;
-    // exponentials shared by all right-hand sides
-    cpx<T> E1[2][Q], E2[H1];
-    auto row_exp = [&](int t2, cpx<T> &e0, cpx<T> &e1) {
-        const int a1 = 2 * fap1 + j1, a2 = 2 * fap2 + j2;
+    // first pass: thread (block bbl, j1, c, t1)
+    const int j1 = rr / (4 * Q), fc = (rr / Q) & 3, t1 = rr % Q;
+    const int fc1 = fc >> 1, fc2 = fc & 1;
+    // kernel value conj-applied to row t1 of child (j1, j2) at column t2
+    auto row_exp = [&](int j2, int t2) __attribute__((always_inline)) {
+        const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
         const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[t2]),
-                                 sj[fb][0][j1][t1], cj[fb][0][j1][t1], sj[fb][1][j2][t2], cj[fb][1][j2][t2]);
-        const double G = phase_dir(xp, ct0[fb][c2f], st0[fb][c2f]);
-        e0 = cis<T>(r0c[fb][0] * G);
-        e1 = cis<T>(r0c[fb][1] * G);
+                                 sj[bbl][0][j1][t1], cj[bbl][0][j1][t1], sj[bbl][1][j2][t2], cj[bbl][1][j2][t2]);
+        return cis<T>(r0c[bbl][fc1] * phase_dir(xp, ct0[bbl][fc2], st0[bbl][fc2]));
     };
-    if (HOIST && factive) {
-#pragma unroll
-        for (int t2 = 0; t2 < Q; ++t2) row_exp(t2, E1[0][t2], E1[1][t2]);
-    }
+    // second pass: thread (h, block sb, c sc, column tp2)
+    const int h = __builtin_amdgcn_readfirstlane(tid / (NT / 2));
+    const int si = tid - h * (NT / 2);
+    const int sb = si / (4 * Q), sk = si - sb * (4 * Q), sc = sk / Q, tp2 = sk - sc * Q;
+    const int sc1 = sc >> 1, sc2 = sc & 1;
+    const size_t sblk = (size_t)blockIdx.x * BPW + sb;
+    const bool sactive = sb < BPW && sblk < nblk;
+    int sap1 = 0, sap2 = 0;
+    if (sactive) morton_decode((uint32_t)(sblk >> (2 * lB)), sap1, sap2);
+    auto pre_exp = [&](int tp1) __attribute__((always_inline)) {  // E(x^{A_p}_t', p0(B_c)) at t' = (tp1, tp2)
+        const XP xp = make_xp_sc(ph, box_node(sap1, level - 1, tb.z[tp1]), box_node(sap2, level - 1, tb.z[tp2]),
+                                 sp[sb][0][tp1], cp[sb][0][tp1], sp[sb][1][tp2], cp[sb][1][tp2]);
+        return cis<T>(r0c[sb][sc1] * phase_dir(xp, ct0[sb][sc2], st0[sb][sc2]));
+    };
+    // exponentials shared by all right-hand sides
+    cpx<T> E1[2][Q], E2[2 * NK];
     if (HOIST && active) {
-        const double xa2 = box_node(ap2, level - 1, tb.z[tp2]);
 #pragma unroll
-        for (int kk = 0; kk < H1; ++kk) {
-            const int tp1 = min(h * H1 + kk, Q - 1);
-            const XP xp = make_xp_sc(ph, box_node(ap1, level - 1, tb.z[tp1]), xa2, sp[bbl][0][tp1],
-                                     cp[bbl][0][tp1], sp[bbl][1][tp2], cp[bbl][1][tp2]);
-            E2[kk] = cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]));
+        for (int t2 = 0; t2 < Q; ++t2) {
+            E1[0][t2] = row_exp(0, t2);
+            E1[1][t2] = row_exp(1, t2);
         }
     }
-    // inputs of the thread's row, loaded one right-hand side ahead
-    cpx<T> nx[Q];
-    auto load_row = [&](int r) {
-        const cpx<T> *src = win + r * plane + ((size_t)(4 * fmAp + 2 * j1 + j2) * nBl + fmB) * QQ + t1 * Q;
+    if (HOIST && sactive) {
 #pragma unroll
-        for (int t2 = 0; t2 < Q; ++t2) nx[t2] = src[t2];
+        for (int k = 0; k < NK; ++k) {
+            const int n = min(h + 2 * k, H1 - 1);
+            E2[2 * k] = pre_exp(n);
+            E2[2 * k + 1] = pre_exp(Q - 1 - n);
+        }
+    }
+    // inputs of the thread's two rows, loaded one right-hand side ahead
+    cpx<T> nx[2][Q];
+    auto load_rows = [&](int r) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j2 = 0; j2 < 2; ++j2) {
+            const cpx<T> *src = win + r * plane + ((size_t)(4 * mAp + 2 * j1 + j2) * nBl + mB) * QQ + t1 * Q;
+#pragma unroll
+            for (int t2 = 0; t2 < Q; ++t2) nx[j2][t2] = src[t2];
+        }
     };
     constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
-    if (PF && factive) load_row(0);
+    if (PF && active) load_rows(0);
+    cpx<T> *const dst0 = wout + (sblk * 4 + sc) * QQ;
     for (int r = 0; r < (HOIST ? nrhs : 1); ++r) {
-        {
-            cpx<T> acc0[Q], acc1[Q];   // c1 = 0, 1
+        opaque_sgpr(SAg);
+        if (active) {
+            if (!PF) load_rows(r);
+            // a = v_0 + J v_1, b = v_0 - J v_1 with v_j2 = conj E . delta of child (j1, j2)
+            cpx<T> P[H1], D[H > 0 ? H : 1];
 #pragma unroll
-            for (int t = 0; t < Q; ++t) acc0[t] = acc1[t] = {(T)0, (T)0};
-            if (factive) {
-                if (!PF) load_row(r);
-                cpx<T> in[Q];
+            for (int n = 0; n < H1; ++n) P[n] = {(T)0, (T)0};
 #pragma unroll
-                for (int k = 0; k < Q; ++k) in[k] = nx[k];
-                if (PF && r + 1 < nrhs) load_row(r + 1);
+            for (int n = 0; n < H; ++n) D[n] = {(T)0, (T)0};
 #pragma unroll
-                for (int t2 = 0; t2 < Q; ++t2) {
-                    cpx<T> e0, e1;
-                    if constexpr (HOIST) {
-                        e0 = E1[0][t2];
-                        e1 = E1[1][t2];
-                    } else {
-                        row_exp(t2, e0, e1);
-                    }
-                    const cpx<T> d = in[t2];
-                    const cpx<T> v0 = cmulc(d, e0);
-                    const cpx<T> v1 = cmulc(d, e1);
+            for (int m = 0; m < Q; ++m) {
+                const cpx<T> v0 = cmulc(nx[0][m], HOIST ? E1[0][m] : row_exp(0, m));
+                const cpx<T> v1 = cmulc(nx[1][Q - 1 - m], HOIST ? E1[1][Q - 1 - m] : row_exp(1, Q - 1 - m));
+                const cpx<T> av = {v0.re + v1.re, v0.im + v1.im};
+                const cpx<T> bv = {v0.re - v1.re, v0.im - v1.im};
 #pragma unroll
-                    for (int p2 = 0; p2 < Q; ++p2) {
-                        const T m = SPLIT ? Mg[(j2 * Q + p2) * Q + t2] : Ms[j2][p2][t2];
-                        crfma(acc0[p2], m, v0);
-                        crfma(acc1[p2], m, v1);
-                    }
-                }
+                for (int n = 0; n < H1; ++n) crfma(P[n], SAg[n * Q + m], av);
+#pragma unroll
+                for (int n = 0; n < H; ++n) crfma(D[n], SAg[QQ + n * Q + m], bv);
             }
-            if constexpr (SPLIT) {
-                if (factive) {
+            cpx<T> *wr = &Y[bbl][j1][fc][t1 * Q];
 #pragma unroll
-                    for (int p2 = 0; p2 < Q; ++p2) {
-                        Y[fb][j2][j1][c2f][t1 * Q + p2] = acc0[p2];        // c = 2*0 + c2
-                        Y[fb][j2][j1][2 + c2f][t1 * Q + p2] = acc1[p2];    // c = 2*1 + c2
-                    }
-                }
-            } else {
-                // add the partner lane's (other j2) partial rows
-#pragma unroll
-                for (int t = 0; t < Q; ++t) {
-                    acc0[t].re += swap_adjacent_lanes(acc0[t].re);
-                    acc0[t].im += swap_adjacent_lanes(acc0[t].im);
-                    acc1[t].re += swap_adjacent_lanes(acc1[t].re);
-                    acc1[t].im += swap_adjacent_lanes(acc1[t].im);
-                }
-                if (factive && j2 == 0) {
-#pragma unroll
-                    for (int p2 = 0; p2 < Q; ++p2) {
-                        Y[fb][0][j1][c2f][t1 * Q + p2] = acc0[p2];
-                        Y[fb][0][j1][2 + c2f][t1 * Q + p2] = acc1[p2];
-                    }
-                }
+            for (int n = 0; n < H; ++n) {
+                wr[n] = {P[n].re + D[n].re, P[n].im + D[n].im};
+                wr[Q - 1 - n] = {P[n].re - D[n].re, P[n].im - D[n].im};
             }
+            if constexpr (Q & 1) wr[H] = P[H];
         }
         lds_barrier();
-        if (active) {
-            cpx<T> acc[H1];
+        // the next right-hand side's rows are loaded during the second pass
+        if (PF && active && r + 1 < nrhs) load_rows(r + 1);
+        if (sactive) with_uniform<0, 2>(h, [&](auto hc) __attribute__((always_inline)) {
+            constexpr int hh = decltype(hc)::value;
+            cpx<T> Pn[NK], Dn[NK];
 #pragma unroll
-            for (int kk = 0; kk < H1; ++kk) acc[kk] = {(T)0, (T)0};
+            for (int k = 0; k < NK; ++k) Pn[k] = Dn[k] = {(T)0, (T)0};
 #pragma unroll
-            for (int jj1 = 0; jj1 < 2; ++jj1) {
-                cpx<T> col[Q];
+            for (int p = 0; p < Q; ++p) {
+                const cpx<T> x0 = Y[sb][0][sc][p * Q + tp2], x1 = Y[sb][1][sc][(Q - 1 - p) * Q + tp2];
+                const cpx<T> av = {x0.re + x1.re, x0.im + x1.im};
+                const cpx<T> bv = {x0.re - x1.re, x0.im - x1.im};
 #pragma unroll
-                for (int tt = 0; tt < Q; ++tt) {
-                    col[tt] = Y[bbl][0][jj1][c][tt * Q + tp2];
-                    if constexpr (SPLIT) {
-                        const cpx<T> o = Y[bbl][NS - 1][jj1][c][tt * Q + tp2];
-                        col[tt].re += o.re;
-                        col[tt].im += o.im;
+                for (int k = 0; k < NK; ++k) {
+                    const int n = hh + 2 * k;
+                    if (n < H1) {
+                        crfma(Pn[k], SAg[n * Q + p], av);
+                        if (n < H) crfma(Dn[k], SAg[QQ + n * Q + p], bv);
                     }
                 }
-#pragma unroll
-                for (int kk = 0; kk < H1; ++kk) {
-                    const int tp1 = min(h * H1 + kk, Q - 1);
-#pragma unroll
-                    for (int tt = 0; tt < Q; ++tt) crfma(acc[kk], Ms[jj1][tp1][tt], col[tt]);
-                }
             }
-            cpx<T> *dst = wout + r * plane + (blk * 4 + c) * QQ;
-            const double xa2 = box_node(ap2, level - 1, tb.z[tp2]);
+            cpx<T> *dst = dst0 + r * plane;
 #pragma unroll
-            for (int kk = 0; kk < H1; ++kk) {
-                const int tp1 = h * H1 + kk;
-                if (tp1 < Q) {
-                    cpx<T> e;
-                    if constexpr (HOIST) {
-                        e = E2[kk];
-                    } else {
-                        const XP xp = make_xp_sc(ph, box_node(ap1, level - 1, tb.z[tp1]), xa2, sp[bbl][0][tp1],
-                                                 cp[bbl][0][tp1], sp[bbl][1][tp2], cp[bbl][1][tp2]);
-                        e = cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]));
+            for (int k = 0; k < NK; ++k) {
+                const int n = hh + 2 * k;
+                if (n < H1) {
+                    const cpx<T> o0 = {Pn[k].re + Dn[k].re, Pn[k].im + Dn[k].im};
+                    dst[n * Q + tp2] = cmul(o0, HOIST ? E2[2 * k] : pre_exp(n));
+                    if (n < H) {
+                        const cpx<T> o1 = {Pn[k].re - Dn[k].re, Pn[k].im - Dn[k].im};
+                        dst[(Q - 1 - n) * Q + tp2] = cmul(o1, HOIST ? E2[2 * k + 1] : pre_exp(Q - 1 - n));
                     }
-                    dst[tp1 * Q + tp2] = cmul(acc[kk], e);
                 }
             }
-        }
+        });
         lds_barrier();
     }
 }
@@ -395,7 +340,7 @@ __global__ __launch_bounds__(NT) void k_switch_adj(Geom g, PhaseDev ph, Tables t
     for (int q0 = 0; q0 < (ONE ? 1 : nrhs); q0 += RC) {
         const int nr = min(RC, nrhs - q0);
         // staged element e = (rc * PPB + p) * Q + t2 of row t1
-        auto fetch = [&](int t1, cpx<T> (&v)[LPT]) {
+        auto fetch = [&](int t1, cpx<T> (&v)[LPT]) __attribute__((always_inline)) {
 #pragma unroll
             for (int k = 0; k < LPT; ++k) {
                 const int e = tid + k * NT;
@@ -405,7 +350,7 @@ __global__ __launch_bounds__(NT) void k_switch_adj(Geom g, PhaseDev ph, Tables t
                     v[k] = w[(size_t)(q0 + rc) * plane + (pair0 + p) * QQ + t1 * Q + t2];
             }
         };
-        auto stash = [&](int buf, const cpx<T> (&v)[LPT]) {
+        auto stash = [&](int buf, const cpx<T> (&v)[LPT]) __attribute__((always_inline)) {
 #pragma unroll
             for (int k = 0; k < LPT; ++k) {
                 const int e = tid + k * NT;
@@ -482,9 +427,17 @@ __global__ __launch_bounds__(NT) void k_switch_adj(Geom g, PhaseDev ph, Tables t
 // p-level^H at level l: from the outputs (A_j, B) back to the inputs (A_p, B_c)
 //   delta^{A_p B_c}_t' = sum_j conj E(x0(A_j), p^{B_c}_t') sum_t M_c1[t1][t'1] M_c2[t2][t'2]
 //                          E(x0(A_j), p^B_t) delta^{A_j B}_t
-// First pass: thread (j, c2, t1) forms row t1 of E delta for output j and
-// contracts it over t2 with M_c2.  Second pass: thread (c, t'2, half)
-// contracts over t1 with M_c1, applies conj E(x0(A_j), p^{B_c}_t') and sums j.
+// Each 1-D pass feeds one input to two children c (the transposes M_c^T):
+// with M_1 = J M_0 J, (M_1^T v)[q-1-n] = (M_0^T J v)[n], so s = v + J v and
+// d = v - J v (first half) give P = ST_n . s and D = AT_n . d with
+// (M_0^T v)[n] = P + D and (M_1^T v)[q-1-n] = P - D: q MACs for two outputs.
+// First pass: thread (h, block, j, t1) forms row t1 of E delta for output j
+// and produces the columns n = h H1 + k of child c2 = 0 and q-1-n of c2 = 1
+// (h the same for two waves).  Second pass: thread (g, block, c2, t'2), g
+// the wave, takes column t'2 of the first-pass rows of c2 and each output
+// j, produces rows n = g, g + 4, ... of child c1 = 0 and q-1-n of c1 = 1,
+// applies conj E(x0(A_j), p^{B_c}_t') and sums j.  The factors are
+// wave-uniform in both passes (SGPR operands).
 template <typename T, int Q, bool HOIST>
 __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables tb, int level,
                                                    const cpx<T> *__restrict__ win,
@@ -494,8 +447,9 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
     constexpr int TPO = 2 * Q;
     constexpr int TPB = 4 * TPO;
     constexpr int BPW = blocks_per_wg<T, Q, 8>();
-    constexpr int H1 = (Q + 1) / 2;
-    __shared__ T Ms[2][Q][Q];             // Ms[c][t][t'] = M_c[t][t']
+    static_assert(BPW * 4 * Q <= NT / 2 && BPW * 2 * Q <= 64, "pass layouts fit the workgroup");
+    constexpr int H1 = (Q + 1) / 2, H = Q / 2;
+    constexpr int NG = (Q + 3) / 4;       // second-pass rows per thread
     __shared__ double rc[BPW][2 * Q], ctc[BPW][2 * Q], stc[BPW][2 * Q];
     __shared__ double rb[BPW][Q], ctb[BPW][Q], stb[BPW][Q];
     __shared__ double Gc[BPW][4][2 * Q], Gb[BPW][4][Q];
@@ -508,9 +462,9 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
     const bool active = bbl < BPW && blk < nblk;
     const int lB = g.L - level;
     const size_t nBl = (size_t)1 << (2 * lB);
+    cptr<T> SAg = to_constant(pick_SA<T>(tb));
+    cptr<T> STg = SAg + 2 * QQ, ATg = SAg + 3 * QQ;  // re-derived per right-hand side
 
-    const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) (&Ms[0][0][0])[i] = Mg[i];
     uint32_t mB = 0, mAp = 0;
     int b1 = 0, b2 = 0, ap1 = 0, ap2 = 0;
     if (active) {
@@ -543,11 +497,8 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
         if (rr < Q) Gb[bbl][j][rr] = phase_dir(xp, ctb[bbl][rr], stb[bbl][rr]);
     }
     lds_barrier();
-    // first pass: the child index c2 is the same for a pair of waves (threads
-    // [128 c2, 128 c2 + 128)), row (block, j, t1) within it, so the factors
-    // M_c2[t2][t'2] are wave-uniform (scalar operands); second pass: thread
-    // (c, t'2, half) of its block, r = c * 2q + h * q + t'2
-    const int fc2 = __builtin_amdgcn_readfirstlane(tid / (NT / 2)), fi = tid - fc2 * (NT / 2);
+    // first pass: thread (fh, block fb, output fj, row t1); fh uniform over two waves
+    const int fh = __builtin_amdgcn_readfirstlane(tid / (NT / 2)), fi = tid - fh * (NT / 2);
     const int fb = fi / (4 * Q), fk = fi - fb * (4 * Q), fj = fk / Q, t1 = fk - fj * Q;
     const size_t fblk = (size_t)blockIdx.x * BPW + fb;
     const bool factive = fb < BPW && fblk < nblk;
@@ -556,27 +507,88 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
         fmB = (uint32_t)(fblk & (nBl - 1));
         fmAp = (uint32_t)(fblk >> (2 * lB));
     }
-    const int c = r / (2 * Q), k = r - c * 2 * Q;
-    const int h = k / Q, tp2 = k - h * Q;
-    const int c1 = c >> 1, c2 = c & 1;
-    // exponentials shared by all right-hand sides
-    cpx<T> E1[Q], E2[4][H1];
+    // second pass: thread (wave sg, block sb, child column c2 sc2, column tp2)
+    const int sg = __builtin_amdgcn_readfirstlane(tid / 64), sl = tid & 63;
+    const int sb = sl / (2 * Q), sk = sl - sb * (2 * Q), sc2 = sk / Q, tp2 = sk - sc2 * Q;
+    const size_t sblk = (size_t)blockIdx.x * BPW + sb;
+    const bool sactive = sb < BPW && sblk < nblk;
+    // this thread's outputs: (c1 = 0, row n), (c1 = 1, row q-1-n), n = sg + 4k
+    auto out_row = [&](int o) __attribute__((always_inline)) {
+        const int n = min(sg + 4 * (o >> 1), Q - 1);
+        return (o & 1) ? Q - 1 - n : n;
+    };
+    cpx<T> *const dst0 = wout + (sblk * 4 + sc2) * QQ;  // child (0, c2); (1, c2) is 2 QQ further
     const double rhoB = factive ? rb[fb][t1] : 0.0;
+
+    auto first_pass = [&](const cpx<T> (&gv)[Q]) __attribute__((always_inline)) {
+        with_uniform<0, 2>(fh, [&](auto hc) __attribute__((always_inline)) {
+        constexpr int fhh = decltype(hc)::value;
+        cpx<T> sv[H1], dv[H > 0 ? H : 1];
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            sv[m] = {gv[m].re + gv[Q - 1 - m].re, gv[m].im + gv[Q - 1 - m].im};
+            dv[m] = {gv[m].re - gv[Q - 1 - m].re, gv[m].im - gv[Q - 1 - m].im};
+        }
+        if constexpr (Q & 1) sv[H] = gv[H];
+#pragma unroll
+        for (int k = 0; k < H1; ++k) {
+            const int n = fhh * H1 + k;
+            if (n < Q) {
+                cpx<T> P = {(T)0, (T)0}, D = {(T)0, (T)0};
+#pragma unroll
+                for (int m = 0; m < H1; ++m) crfma(P, STg[n * Q + m], sv[m]);
+#pragma unroll
+                for (int m = 0; m < H; ++m) crfma(D, ATg[n * Q + m], dv[m]);
+                Y[fb][0][fj][t1 * Q + n] = {P.re + D.re, P.im + D.im};
+                Y[fb][1][fj][t1 * Q + Q - 1 - n] = {P.re - D.re, P.im - D.im};
+            }
+        }
+        });
+    };
+    // second pass for output jj: z[o] = (M_c1^T col)[row] of this thread's outputs
+    auto second_pass_j = [&](auto gc, int jj, cpx<T> (&z)[2 * NG]) __attribute__((always_inline)) {
+        constexpr int gg = decltype(gc)::value;
+        cpx<T> sv[H1], dv[H > 0 ? H : 1];
+        const cpx<T> *col = &Y[sb][sc2][jj][tp2];
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const cpx<T> x0 = col[m * Q], x1 = col[(Q - 1 - m) * Q];
+            sv[m] = {x0.re + x1.re, x0.im + x1.im};
+            dv[m] = {x0.re - x1.re, x0.im - x1.im};
+        }
+        if constexpr (Q & 1) sv[H] = col[H * Q];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int n = gg + 4 * k;
+            z[2 * k] = z[2 * k + 1] = {(T)0, (T)0};
+            if (n < Q) {
+                cpx<T> P = {(T)0, (T)0}, D = {(T)0, (T)0};
+#pragma unroll
+                for (int m = 0; m < H1; ++m) crfma(P, STg[n * Q + m], sv[m]);
+#pragma unroll
+                for (int m = 0; m < H; ++m) crfma(D, ATg[n * Q + m], dv[m]);
+                z[2 * k] = {P.re + D.re, P.im + D.im};
+                z[2 * k + 1] = {P.re - D.re, P.im - D.im};
+            }
+        }
+    };
+    // exponentials shared by all right-hand sides
+    cpx<T> E1[Q], E2[4][2 * NG];
     if (HOIST && factive) {
 #pragma unroll
         for (int t2 = 0; t2 < Q; ++t2) E1[t2] = cis<T>(rhoB * Gb[fb][fj][t2]);
     }
-    if (HOIST && active) {
+    if (HOIST && sactive) {
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
-            const double G = Gc[bbl][jj][c2 * Q + tp2];
+            const double G = Gc[sb][jj][sc2 * Q + tp2];
 #pragma unroll
-            for (int kk = 0; kk < H1; ++kk) E2[jj][kk] = cis<T>(rc[bbl][c1 * Q + min(h * H1 + kk, Q - 1)] * G);
+            for (int o = 0; o < 2 * NG; ++o) E2[jj][o] = cis<T>(rc[sb][(o & 1) * Q + out_row(o)] * G);
         }
     }
     // inputs of the thread's row, loaded one right-hand side ahead
     cpx<T> nx[Q];
-    auto load_row = [&](int ri) {
+    auto load_row = [&](int ri) __attribute__((always_inline)) {
         const cpx<T> *src = win + ri * plane + ((size_t)(4 * fmAp + fj) * nBl + fmB) * QQ + t1 * Q;
 #pragma unroll
         for (int t2 = 0; t2 < Q; ++t2) nx[t2] = src[t2];
@@ -584,55 +596,48 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
     constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
     if (PF && factive) load_row(0);
     for (int ri = 0; ri < (HOIST ? nrhs : 1); ++ri) {
+        opaque_sgpr(SAg);
+        STg = SAg + 2 * QQ;
+        ATg = SAg + 3 * QQ;
         if (factive) {
             if (!PF) load_row(ri);
-            cpx<T> in[Q];
+            cpx<T> gv[Q];
 #pragma unroll
-            for (int k = 0; k < Q; ++k) in[k] = nx[k];
-            cpx<T> acc[Q];
-#pragma unroll
-            for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
-#pragma unroll
-            for (int t2 = 0; t2 < Q; ++t2) {
-                const cpx<T> gv = cmul(in[t2], HOIST ? E1[t2] : cis<T>(rhoB * Gb[fb][fj][t2]));
-#pragma unroll
-                for (int p2 = 0; p2 < Q; ++p2) crfma(acc[p2], Mg[(fc2 * Q + t2) * Q + p2], gv);
-            }
-#pragma unroll
-            for (int p2 = 0; p2 < Q; ++p2) Y[fb][fc2][fj][t1 * Q + p2] = acc[p2];
+            for (int t2 = 0; t2 < Q; ++t2) gv[t2] = cmul(nx[t2], HOIST ? E1[t2] : cis<T>(rhoB * Gb[fb][fj][t2]));
+            first_pass(gv);
         }
         lds_barrier();
         // the next right-hand side's row is loaded during the (longer) second
         // pass (issuing it before the first pass measured slower)
         if (PF && factive && ri + 1 < nrhs) load_row(ri + 1);
-        if (active) {
-            cpx<T> acc[H1];
+        if (sactive) with_uniform<0, 4>(sg, [&](auto gc) __attribute__((always_inline)) {
+            constexpr int gg = decltype(gc)::value;
+            cpx<T> acc[2 * NG];
 #pragma unroll
-            for (int kk = 0; kk < H1; ++kk) acc[kk] = {(T)0, (T)0};
-#pragma unroll(HOIST ? 4 : 1)
+            for (int o = 0; o < 2 * NG; ++o) acc[o] = {(T)0, (T)0};
+#pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
-                cpx<T> col[Q];
+                cpx<T> z[2 * NG];
+                second_pass_j(gc, jj, z);
+                const double G = Gc[sb][jj][sc2 * Q + tp2];
 #pragma unroll
-                for (int tt = 0; tt < Q; ++tt) col[tt] = Y[bbl][c2][jj][tt * Q + tp2];
-                const double G = Gc[bbl][jj][c2 * Q + tp2];
-#pragma unroll
-                for (int kk = 0; kk < H1; ++kk) {
-                    const int tp1 = min(h * H1 + kk, Q - 1);
-                    cpx<T> z = {(T)0, (T)0};
-#pragma unroll
-                    for (int tt = 0; tt < Q; ++tt) crfma(z, Ms[c1][tt][tp1], col[tt]);
-                    const cpx<T> add = cmulc(z, HOIST ? E2[jj][kk] : cis<T>(rc[bbl][c1 * Q + tp1] * G));
-                    acc[kk].re += add.re;
-                    acc[kk].im += add.im;
+                for (int o = 0; o < 2 * NG; ++o) {
+                    const cpx<T> add =
+                        cmulc(z[o], HOIST ? E2[jj][o] : cis<T>(rc[sb][(o & 1) * Q + out_row(o)] * G));
+                    acc[o].re += add.re;
+                    acc[o].im += add.im;
                 }
             }
-            cpx<T> *dst = wout + ri * plane + (blk * 4 + c) * QQ;
+            cpx<T> *dst = dst0 + ri * plane;
 #pragma unroll
-            for (int kk = 0; kk < H1; ++kk) {
-                const int tp1 = h * H1 + kk;
-                if (tp1 < Q) dst[tp1 * Q + tp2] = acc[kk];
+            for (int k = 0; k < NG; ++k) {
+                const int n = gg + 4 * k;
+                if (n < Q) {
+                    dst[n * Q + tp2] = acc[2 * k];
+                    dst[2 * QQ + (Q - 1 - n) * Q + tp2] = acc[2 * k + 1];
+                }
             }
-        }
+        });
         lds_barrier();
     }
 }
@@ -736,7 +741,7 @@ static hipError_t xlevel_adj_t(const Geom &g, const PhaseDev &ph, const Tables &
     const unsigned nblk = 1u << (2 * g.L - 2);
 #define L_XLA(Q)                                                                                     \
     {                                                                                                \
-        constexpr int BPW = blocks_per_wg<T, Q, 8 * (xadj_split<T, Q>() ? 2 : 1)>();               \
+        constexpr int BPW = blocks_per_wg<T, Q, 8>();                                                \
         const dim3 grid((nblk + BPW - 1) / BPW);                                                     \
         if (nrhs == 1)                                                                               \
             hipLaunchKernelGGL((k_xlevel_adj<T, Q, false>), grid, dim3(NT), 0, st, g, ph, tb, level, \

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fio_device.h"
 
 namespace fio {
@@ -44,6 +46,13 @@ template <>
 __device__ __forceinline__ const float *pick_M<float>(const Tables &tb) { return tb.Mf; }
 template <>
 __device__ __forceinline__ const double *pick_M<double>(const Tables &tb) { return tb.M; }
+
+template <typename T>
+__device__ __forceinline__ const T *pick_SA(const Tables &tb);
+template <>
+__device__ __forceinline__ const float *pick_SA<float>(const Tables &tb) { return tb.SAf; }
+template <>
+__device__ __forceinline__ const double *pick_SA<double>(const Tables &tb) { return tb.SA; }
 
 template <typename T>
 __device__ __forceinline__ const T *pick_T(const Tables &tb);
@@ -108,6 +117,40 @@ __device__ __forceinline__ double swap_adjacent_lanes(double x) {
     const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, true);
     const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// f(std::integral_constant<int, v>) for a wave-uniform v in [I, N): code that
+// indexes wave-uniform tables by v is then compiled once per value, with the
+// table offsets known (batched scalar loads, no per-element branches).
+template <int I, int N, typename F>
+__device__ __forceinline__ void with_uniform(int v, F &&f) {
+    if constexpr (I < N) {
+        if (v == I)
+            f(std::integral_constant<int, I>{});
+        else
+            with_uniform<I + 1, N>(v, f);
+    }
+}
+
+// A pointer into the constant address space: wave-uniform loads through it
+// are scalar loads (s_load, through the scalar cache) whatever the stores
+// around them.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> to_constant(const T *p) {
+    return (cptr<T>)p;
+}
+
+// Makes a wave-uniform pointer opaque to the optimiser (an empty asm that
+// claims to update the SGPR pair holding it).  Called once per right-hand
+// side on the interpolation-table pointer, it keeps the table's scalar
+// loads (scalar-cache hits) inside the loop: as loop invariants the compiler
+// would hoist them, and with more table values than SGPRs it parks them in
+// VGPRs for the whole loop, costing waves per SIMD.
+template <typename T>
+__device__ __forceinline__ void opaque_sgpr(cptr<T> &p) {
+    asm volatile("" : "+s"(p));
 }
 
 #define FIO_DISPATCH_Q(q, MACRO) \

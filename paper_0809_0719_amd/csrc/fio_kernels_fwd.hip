@@ -118,12 +118,18 @@ __global__ __launch_bounds__(NT) void k_init(Geom g, PhaseDev ph, Tables tb, Sou
 //   delta^{AB}_t = conj E(x0(A), p^B_t) sum_c sum_t' M_c1[t1][t'1] M_c2[t2][t'2]
 //                     E(x0(A), p^{B_c}_t') delta^{A_p B_c}_t'
 // for the four children A of A_p.  The q x q Kronecker sum over the four
-// children B_c is done one dimension at a time (Sec. 4: 6 q^3 per pair).
-// Each output pair gets 2q threads: in the first pass thread (c1, t'1)
-// forms its prefactored row of the two children (c1, 0), (c1, 1) in
-// registers and contracts it against M_c2 (read as LDS broadcasts); in the
-// second pass thread (t2, half) takes column t2 and produces half the rows
-// t1, remodulated and stored.
+// children B_c is done one dimension at a time (Sec. 4), each 1-D pass
+// summing two children: with M_1 = J M_0 J (the nodes are symmetric),
+//   M_0 u + M_1 y = S (u + J y) + A (u - J y),
+// S and A the symmetric and antisymmetric halves of M_0 by rows, whose rows
+// n and q-1-n agree up to sign -- so P = S_n . a and D = A_n . b give both
+// outputs n (P + D) and q-1-n (P - D): q MACs per output instead of 2q.
+// First pass: thread (block, j, c1, t'1) forms its prefactored row of the
+// two children (c1, 0), (c1, 1) in registers and contracts it against S
+// and A.  Second pass: thread (h, block, j, t2) takes column t2 of output j
+// and the row pairs n = h, h + 2, ...; h is the same for a half of the
+// workgroup (two waves), so in both passes the factors are wave-uniform
+// (SGPR operands through the scalar cache).
 // ===========================================================================
 template <typename T, int Q, bool HOIST>
 __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, int level,
@@ -131,12 +137,12 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
                                                cpx<T> *__restrict__ wout, unsigned nblk,
                                                int nrhs, size_t plane) {
     constexpr int QQ = Q * Q;
-    constexpr int TPO = 2 * Q;            // threads per output pair
-    constexpr int TPB = 4 * TPO;          // threads per butterfly block
+    constexpr int TPO = 2 * Q;            // first-pass threads per output pair
+    constexpr int TPB = 4 * TPO;          // first-pass threads per butterfly block
     constexpr int BPW = blocks_per_wg<T, Q, 8>();
-    constexpr int H1 = (Q + 1) / 2;
-    __shared__ T Mt[2][Q][Q];             // Mt[c][t'][t] = M_c[t][t']
-    __shared__ T Ms[2][Q][Q];             // Ms[c][t][t'] = M_c[t][t']
+    static_assert(BPW * 4 * Q <= NT / 2, "second pass: a block's columns fit a half workgroup");
+    constexpr int H1 = (Q + 1) / 2, H = Q / 2;
+    constexpr int NK = (H1 + 1) / 2;      // row pairs per second-pass thread
     __shared__ double rc[BPW][2 * Q], ctc[BPW][2 * Q], stc[BPW][2 * Q];  // child nodes: rho(c1,t'), theta(c2,t')
     __shared__ double rb[BPW][Q], ctb[BPW][Q], stb[BPW][Q];              // B's nodes
     __shared__ double Gc[BPW][4][2 * Q], Gb[BPW][4][Q];
@@ -149,13 +155,8 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
     const bool active = bbl < BPW && blk < nblk;
     const int lB = g.L - level;
     const size_t nBl = (size_t)1 << (2 * lB);
+    cptr<T> SAg = to_constant(pick_SA<T>(tb));
 
-    const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) {
-        const int c = i / QQ, t = (i - c * QQ) / Q, tp = i - c * QQ - t * Q;
-        Ms[c][t][tp] = Mg[i];
-        Mt[c][tp][t] = Mg[i];
-    }
     uint32_t mB = 0, mAp = 0;
     int b1 = 0, b2 = 0, ap1 = 0, ap2 = 0;
     if (active) {
@@ -188,23 +189,36 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
         if (rr < Q) Gb[bbl][j][rr] = phase_dir(xp, ctb[bbl][rr], stb[bbl][rr]);
     }
     lds_barrier();
-    // exponentials of this thread's row (first pass) and column (second
-    // pass), shared by all right-hand sides
+    // first-pass row (c1, t'1)
     const int c1 = rr / Q, tp1 = rr - c1 * Q;
-    const int h = rr / Q, t2 = rr - h * Q;
-    cpx<T> Ea[2 * Q], Eb[H1];
-    const double rhoA = rc[bbl][rr], GB = Gb[bbl][j][t2];
+    const double rhoA = rc[bbl][rr];
+    // second-pass column: (h, block sb, output sj, column st2)
+    const int h = __builtin_amdgcn_readfirstlane(tid / (NT / 2));
+    const int si = tid - h * (NT / 2);
+    const int sb = si / (4 * Q), sk = si - sb * (4 * Q), sj = sk / Q, st2 = sk - sj * Q;
+    const size_t sblk = (size_t)blockIdx.x * BPW + sb;
+    const bool sactive = sb < BPW && sblk < nblk;
+    const double GB = sactive ? Gb[sb][sj][st2] : 0.0;
+    // exponentials of the first-pass row and of the second-pass rows, shared
+    // by all right-hand sides
+    cpx<T> Ea[2 * Q], Eb[2 * NK];
     if constexpr (HOIST) {
         if (active) {
 #pragma unroll
             for (int k = 0; k < 2 * Q; ++k) Ea[k] = cis<T>(rhoA * Gc[bbl][j][k]);
+        }
+        if (sactive) {
 #pragma unroll
-            for (int k = 0; k < H1; ++k) Eb[k] = cis<T>(rb[bbl][min(h * H1 + k, Q - 1)] * GB);
+            for (int k = 0; k < NK; ++k) {
+                const int n = min(h + 2 * k, H1 - 1);
+                Eb[2 * k] = cis<T>(rb[sb][n] * GB);
+                Eb[2 * k + 1] = cis<T>(rb[sb][Q - 1 - n] * GB);
+            }
         }
     }
     // inputs of the thread's row, loaded one right-hand side ahead
     cpx<T> nx[2 * Q];
-    auto load_row = [&](int r) {
+    auto load_row = [&](int r) __attribute__((always_inline)) {
 #pragma unroll
         for (int c2 = 0; c2 < 2; ++c2) {
             const cpx<T> *src = win + r * plane + (blk * 4 + 2 * c1 + c2) * QQ + tp1 * Q;
@@ -214,52 +228,80 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
     };
     constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
     if (PF && active) load_row(0);
+    cpx<T> *const dst0 = wout + ((size_t)(4 * (sblk >> (2 * lB)) + sj) * nBl + (sblk & (nBl - 1))) * QQ;
     for (int r = 0; r < (HOIST ? nrhs : 1); ++r) {
+        opaque_sgpr(SAg);
         if (active) {
             if (!PF) load_row(r);
             const cpx<T>(&in)[2 * Q] = nx;
-            // first pass: row (c1, t'1)
-            cpx<T> acc[Q];
+            // first pass: row (c1, t'1); a = v_0 + J v_1, b = v_0 - J v_1
+            cpx<T> P[H1], D[H > 0 ? H : 1];
 #pragma unroll
-            for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
+            for (int n = 0; n < H1; ++n) P[n] = {(T)0, (T)0};
 #pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2) {
+            for (int n = 0; n < H; ++n) D[n] = {(T)0, (T)0};
 #pragma unroll
-                for (int tp2 = 0; tp2 < Q; ++tp2) {
-                    const cpx<T> e = HOIST ? Ea[c2 * Q + tp2] : cis<T>(rhoA * Gc[bbl][j][c2 * Q + tp2]);
-                    const cpx<T> v = cmul(e, in[c2 * Q + tp2]);
-                    // M_c2[tt][t'2]: the same for every thread, read through the
-                    // scalar cache (SGPR operands) rather than as LDS broadcasts
+            for (int m = 0; m < Q; ++m) {
+                const cpx<T> e0 = HOIST ? Ea[m] : cis<T>(rhoA * Gc[bbl][j][m]);
+                const cpx<T> e1 = HOIST ? Ea[2 * Q - 1 - m] : cis<T>(rhoA * Gc[bbl][j][2 * Q - 1 - m]);
+                const cpx<T> v0 = cmul(e0, in[m]);
+                const cpx<T> v1 = cmul(e1, in[2 * Q - 1 - m]);
+                const cpx<T> av = {v0.re + v1.re, v0.im + v1.im};
+                const cpx<T> bv = {v0.re - v1.re, v0.im - v1.im};
 #pragma unroll
-                    for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Mg[(c2 * Q + tt) * Q + tp2], v);
-                }
+                for (int n = 0; n < H1; ++n) crfma(P[n], SAg[n * Q + m], av);
+#pragma unroll
+                for (int n = 0; n < H; ++n) crfma(D[n], SAg[QQ + n * Q + m], bv);
             }
+            cpx<T> *wr = &W[bbl][j][rr * Q];
 #pragma unroll
-            for (int tt = 0; tt < Q; ++tt) W[bbl][j][rr * Q + tt] = acc[tt];
+            for (int n = 0; n < H; ++n) {
+                wr[n] = {P[n].re + D[n].re, P[n].im + D[n].im};
+                wr[Q - 1 - n] = {P[n].re - D[n].re, P[n].im - D[n].im};
+            }
+            if constexpr (Q & 1) wr[H] = P[H];
         }
         lds_barrier();
         // the next right-hand side's row is loaded during the second pass, once
         // the first pass has consumed this one
         if (PF && active && r + 1 < nrhs) load_row(r + 1);
-        if (active) {
-            // second pass: column t2, rows t1 of one half, then remodulation
-            cpx<T> col[2 * Q];
+        if (sactive) with_uniform<0, 2>(h, [&](auto hc) __attribute__((always_inline)) {
+            constexpr int hh = decltype(hc)::value;
+            // second pass: column st2 over c1 (a = W_0 + J W_1, b = W_0 - J W_1),
+            // row pairs n = hh + 2k, then remodulation
+            cpx<T> Pn[NK], Dn[NK];
 #pragma unroll
-            for (int k = 0; k < 2 * Q; ++k) col[k] = W[bbl][j][k * Q + t2];
-            cpx<T> *dst = wout + r * plane + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
+            for (int k = 0; k < NK; ++k) Pn[k] = Dn[k] = {(T)0, (T)0};
 #pragma unroll
-            for (int k = 0; k < H1; ++k) {
-                const int t1 = h * H1 + k;
-                if (t1 < Q) {
-                    cpx<T> o = {(T)0, (T)0};
+            for (int p = 0; p < Q; ++p) {
+                const cpx<T> x0 = W[sb][sj][p * Q + st2], x1 = W[sb][sj][(2 * Q - 1 - p) * Q + st2];
+                const cpx<T> av = {x0.re + x1.re, x0.im + x1.im};
+                const cpx<T> bv = {x0.re - x1.re, x0.im - x1.im};
 #pragma unroll
-                    for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-                        for (int p1 = 0; p1 < Q; ++p1) crfma(o, Ms[cc][t1][p1], col[cc * Q + p1]);
-                    dst[t1 * Q + t2] = cmulc(o, HOIST ? Eb[k] : cis<T>(rb[bbl][t1] * GB));
+                for (int k = 0; k < NK; ++k) {
+                    constexpr int n0 = hh;
+                    const int n = n0 + 2 * k;
+                    if (n < H1) {
+                        crfma(Pn[k], SAg[n * Q + p], av);
+                        if (n < H) crfma(Dn[k], SAg[QQ + n * Q + p], bv);
+                    }
                 }
             }
-        }
+            cpx<T> *dst = dst0 + r * plane;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const int n = hh + 2 * k;
+                if (n < H1) {
+                    const cpx<T> o0 = {Pn[k].re + Dn[k].re, Pn[k].im + Dn[k].im};
+                    dst[n * Q + st2] = cmulc(o0, HOIST ? Eb[2 * k] : cis<T>(rb[sb][n] * GB));
+                    if (n < H) {
+                        const cpx<T> o1 = {Pn[k].re - Dn[k].re, Pn[k].im - Dn[k].im};
+                        dst[(Q - 1 - n) * Q + st2] =
+                            cmulc(o1, HOIST ? Eb[2 * k + 1] : cis<T>(rb[sb][Q - 1 - n] * GB));
+                    }
+                }
+            }
+        });
         lds_barrier();
     }
 }
@@ -374,13 +416,22 @@ __global__ __launch_bounds__(NT) void k_switch(Geom g, PhaseDev ph, Tables tb, c
 //   delta^{AB}_t = sum_c E(x^A_t, p0(B_c)) sum_t' M_a1[t'1][t1] M_a2[t'2][t2]
 //                    conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t'
 // for the four children A = (a1, a2) of A_p.  The prefactor depends only on
-// (A_p, B_c); the first (second-dimension) pass depends on A only through
-// a2, so it is shared by the children with the same a2.  Threads: first pass
-// (a2, c, t'1) rows; second pass (A, t2, half) columns with the remodulation
-// per B_c.  One right-hand side: the prefactor is applied once per row
-// (c, t'1) in a phase of its own.  Several: every first-pass thread applies
-// its row's prefactor itself (kernel values hoisted for all right-hand
-// sides), which saves a barrier per right-hand side.
+// (A_p, B_c).  Each 1-D pass feeds one input to two children (a = 0, 1):
+// with M_1 = J M_0 J, (M_1^T v)[q-1-n] = (M_0^T J v)[n], so splitting v into
+// s = v + J v and d = v - J v (first half) gives P = ST_n . s and
+// D = AT_n . d with (M_0^T v)[n] = P + D and (M_1^T v)[q-1-n] = P - D:
+// q MACs for two outputs instead of 2q.
+// First pass (second dimension): thread (h, block, c, t'1) forms the
+// prefactored row (c, t'1) and produces the outputs n = h H1 + k of child
+// a2 = 0 and q-1-n of a2 = 1; h is the same for two waves.  Second pass
+// (first dimension): thread (g, block, a2, t2), g the wave, takes column t2
+// of the first-pass rows of a2, produces rows n = g, g + 4, ... of child
+// a1 = 0 and q-1-n of a1 = 1, remodulates by E(x^A_t, p0(B_c)) and sums
+// over c.  The factors are wave-uniform in both passes (SGPR operands).
+// One right-hand side: the prefactor is applied once per row (c, t'1) in a
+// phase of its own.  Several: every first-pass thread applies its row's
+// prefactor itself (kernel values hoisted for all right-hand sides), which
+// saves a barrier per right-hand side.
 // ===========================================================================
 template <typename T, int Q, bool HOIST>
 __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, int level,
@@ -390,9 +441,10 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
     constexpr int QQ = Q * Q;
     constexpr int TPB = 8 * Q;
     constexpr int BPW = blocks_per_wg<T, Q, 12>();
-    constexpr int H1 = (Q + 1) / 2;
-    __shared__ T Ms[2][Q][Q];                       // Ms[a][t'][t] = M_a[t'][t]
-    __shared__ cpx<T> v[BPW][4][QQ];                // prefactored inputs [c][t'1][t'2]
+    static_assert(BPW * 4 * Q <= NT / 2 && BPW * 2 * Q <= 64, "pass layouts fit the workgroup");
+    constexpr int H1 = (Q + 1) / 2, H = Q / 2;
+    constexpr int NG = (Q + 3) / 4;                 // second-pass rows per thread
+    __shared__ cpx<T> v[BPW][4][QQ];                // prefactored inputs [c][t'1][t'2] (one RHS)
     __shared__ cpx<T> Y[BPW][2][4][QQ];             // first pass [a2][c][t'1][t2]
     __shared__ double sp[BPW][2][Q], cp[BPW][2][Q];        // sin/cos(2 pi x) at A_p's nodes, per dim
     __shared__ double sj[BPW][2][2][Q], cj[BPW][2][2][Q];  // at the children's nodes [dim][a][t]
@@ -405,9 +457,9 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
     const int lB = g.L - level;
     const size_t nBl = (size_t)1 << (2 * lB);
     const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
+    cptr<T> SAg = to_constant(pick_SA<T>(tb));
+    cptr<T> STg = SAg + 2 * QQ, ATg = SAg + 3 * QQ;  // re-derived per right-hand side
 
-    const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) (&Ms[0][0][0])[i] = Mg[i];
     uint32_t mB = 0, mAp = 0;
     int b1 = 0, b2 = 0, ap1 = 0, ap2 = 0;
     if (active) {
@@ -437,112 +489,160 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
         }
     }
     lds_barrier();
-    // exponentials shared by all right-hand sides: the prefactor row (c, t'1)
-    // of threads rr < 4q, and the remodulation E(x^A_t, p0(B_c)) of the
-    // second-pass column (A, t2, half) of every thread
-    const int pc = rr / Q, ptp1 = rr - pc * Q;          // prefactor row (rr < 4q)
-    const int a2c = rr / (4 * Q), ak = rr - a2c * 4 * Q;
-    const int ac = ak / Q, atp1 = ak - ac * Q;          // first-pass row
-    const int jj = rr / (2 * Q), bk = rr - jj * 2 * Q;
-    const int h = bk / Q, t2 = bk - h * Q;              // second-pass column
-    const int j1 = jj >> 1, j2 = jj & 1;
-    cpx<T> Ep[Q], E2[4][H1];
-    auto pre_exp = [&](int tp2) -> cpx<T> {
-        const int c2 = pc & 1, c1 = pc >> 1;
-        const XP xp = make_xp_sc(ph, box_node(ap1, level - 1, tb.z[ptp1]), box_node(ap2, level - 1, tb.z[tp2]),
-                                 sp[bbl][0][ptp1], cp[bbl][0][ptp1], sp[bbl][1][tp2], cp[bbl][1][tp2]);
-        return cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2]));
-    };
-    // batched first pass: the child's a2 is the same for a pair of waves
-    // (threads [128 a2, 128 a2 + 128)), row (block, c, t'1) within it, so the
-    // factors M_a2[t'2][t2] are wave-uniform (scalar operands)
-    // (fa2 is uniform over the wave: make that explicit for the compiler)
-    const int fa2 = __builtin_amdgcn_readfirstlane(tid / (NT / 2)), fi = tid - fa2 * (NT / 2);
+    // first pass: thread (fh, block fb, c fac, row fatp1); fh uniform over two waves
+    const int fh = __builtin_amdgcn_readfirstlane(tid / (NT / 2)), fi = tid - fh * (NT / 2);
     const int fb = fi / (4 * Q), fk = fi - fb * (4 * Q), fac = fk / Q, fatp1 = fk - fac * Q;
     const size_t fblk = (size_t)blockIdx.x * BPW + fb;
     const bool factive = fb < BPW && fblk < nblk;
     int fap1 = 0, fap2 = 0;
     if (factive) morton_decode((uint32_t)(fblk >> (2 * lB)), fap1, fap2);
-    if (HOIST && factive) {
-        // every first-pass thread applies the prefactor of its own row (c, t'1)
-        const int c2 = fac & 1, c1 = fac >> 1;
-        const double xa1 = box_node(fap1, level - 1, tb.z[fatp1]);
+    // second pass: thread (wave sg, block sb, a2 sj2, column st2)
+    const int sg = __builtin_amdgcn_readfirstlane(tid / 64), sl = tid & 63;
+    const int sb = sl / (2 * Q), sk = sl - sb * (2 * Q), sj2 = sk / Q, st2 = sk - sj2 * Q;
+    const size_t sblk = (size_t)blockIdx.x * BPW + sb;
+    const bool sactive = sb < BPW && sblk < nblk;
+    int sap1 = 0, sap2 = 0;
+    if (sactive) morton_decode((uint32_t)(sblk >> (2 * lB)), sap1, sap2);
+    // remodulation phases of this thread's outputs: (a1 = 0, row n), (a1 = 1, row q-1-n)
+    // for n = sg + 4k, against theta0(B_c2); G[c2][2k + side]
+    auto out_row = [&](int k, int side) __attribute__((always_inline)) {
+        const int n = min(sg + 4 * k, Q - 1);
+        return side ? Q - 1 - n : n;
+    };
+    auto remod_phase = [&](int k, int side, int c2) __attribute__((always_inline)) {
+        const int a1 = 2 * sap1 + side, a2 = 2 * sap2 + sj2, t1 = out_row(k, side);
+        const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[st2]),
+                                 sj[sb][0][side][t1], cj[sb][0][side][t1], sj[sb][1][sj2][st2],
+                                 cj[sb][1][sj2][st2]);
+        return phase_dir(xp, ct0[sb][c2], st0[sb][c2]);
+    };
+    cpx<T> *const dst0 = wout + ((size_t)(4 * (sblk >> (2 * lB)) + sj2) * nBl + (sblk & (nBl - 1))) * QQ;
+    cpx<T> *const dst1 = dst0 + 2 * nBl * QQ;  // child (1, a2)
+
+    // first pass on the prefactored row vv (both children a2)
+    auto first_pass = [&](const cpx<T> (&vv)[Q]) __attribute__((always_inline)) {
+        with_uniform<0, 2>(fh, [&](auto hc) __attribute__((always_inline)) {
+        constexpr int fhh = decltype(hc)::value;
+        cpx<T> sv[H1], dv[H > 0 ? H : 1];
 #pragma unroll
-        for (int tp2 = 0; tp2 < Q; ++tp2) {
-            const XP xp = make_xp_sc(ph, xa1, box_node(fap2, level - 1, tb.z[tp2]), sp[fb][0][fatp1],
-                                     cp[fb][0][fatp1], sp[fb][1][tp2], cp[fb][1][tp2]);
-            Ep[tp2] = cis<T>(r0c[fb][c1] * phase_dir(xp, ct0[fb][c2], st0[fb][c2]));
+        for (int m = 0; m < H; ++m) {
+            sv[m] = {vv[m].re + vv[Q - 1 - m].re, vv[m].im + vv[Q - 1 - m].im};
+            dv[m] = {vv[m].re - vv[Q - 1 - m].re, vv[m].im - vv[Q - 1 - m].im};
         }
-    }
-    if (HOIST && active) {
-        const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
-        const double xb2 = box_node(a2, level, tb.z[t2]);
+        if constexpr (Q & 1) sv[H] = vv[H];
 #pragma unroll
-        for (int kk = 0; kk < H1; ++kk) {
-            const int t1 = min(h * H1 + kk, Q - 1);
-            const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), xb2, sj[bbl][0][j1][t1],
-                                     cj[bbl][0][j1][t1], sj[bbl][1][j2][t2], cj[bbl][1][j2][t2]);
-            const double G0 = phase_dir(xp, ct0[bbl][0], st0[bbl][0]);
-            const double G1 = phase_dir(xp, ct0[bbl][1], st0[bbl][1]);
-            E2[0][kk] = cis<T>(r0c[bbl][0] * G0);
-            E2[1][kk] = cis<T>(r0c[bbl][0] * G1);
-            E2[2][kk] = cis<T>(r0c[bbl][1] * G0);
-            E2[3][kk] = cis<T>(r0c[bbl][1] * G1);
+        for (int k = 0; k < H1; ++k) {
+            const int n = fhh * H1 + k;
+            if (n < Q) {
+                cpx<T> P = {(T)0, (T)0}, D = {(T)0, (T)0};
+#pragma unroll
+                for (int m = 0; m < H1; ++m) crfma(P, STg[n * Q + m], sv[m]);
+#pragma unroll
+                for (int m = 0; m < H; ++m) crfma(D, ATg[n * Q + m], dv[m]);
+                Y[fb][0][fac][fatp1 * Q + n] = {P.re + D.re, P.im + D.im};
+                Y[fb][1][fac][fatp1 * Q + Q - 1 - n] = {P.re - D.re, P.im - D.im};
+            }
         }
-    }
+        });
+    };
+    // second pass for one c, accumulated into out[2k + side]
+    auto second_pass_c = [&](auto gc, int c, cpx<T> (&z)[2 * NG]) __attribute__((always_inline)) {
+        constexpr int gg = decltype(gc)::value;
+        cpx<T> sv[H1], dv[H > 0 ? H : 1];
+        const cpx<T> *col = &Y[sb][sj2][c][st2];
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const cpx<T> x0 = col[m * Q], x1 = col[(Q - 1 - m) * Q];
+            sv[m] = {x0.re + x1.re, x0.im + x1.im};
+            dv[m] = {x0.re - x1.re, x0.im - x1.im};
+        }
+        if constexpr (Q & 1) sv[H] = col[H * Q];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int n = gg + 4 * k;
+            z[2 * k] = z[2 * k + 1] = {(T)0, (T)0};
+            if (n < Q) {
+                cpx<T> P = {(T)0, (T)0}, D = {(T)0, (T)0};
+#pragma unroll
+                for (int m = 0; m < H1; ++m) crfma(P, STg[n * Q + m], sv[m]);
+#pragma unroll
+                for (int m = 0; m < H; ++m) crfma(D, ATg[n * Q + m], dv[m]);
+                z[2 * k] = {P.re + D.re, P.im + D.im};
+                z[2 * k + 1] = {P.re - D.re, P.im - D.im};
+            }
+        }
+    };
+    auto store_outputs = [&](auto gc, const cpx<T> (&out)[2 * NG], size_t off) __attribute__((always_inline)) {
+        constexpr int gg = decltype(gc)::value;
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int n = gg + 4 * k;
+            if (n < Q) {
+                dst0[off + n * Q + st2] = out[2 * k];
+                dst1[off + (Q - 1 - n) * Q + st2] = out[2 * k + 1];
+            }
+        }
+    };
+
     if constexpr (HOIST) {
+        // exponentials shared by all right-hand sides: the prefactor of the
+        // first-pass row (every first-pass thread applies its own) and the
+        // remodulation of the second-pass outputs
+        cpx<T> Ep[Q], E2[4][2 * NG];
+        if (factive) {
+            const int c2 = fac & 1, c1 = fac >> 1;
+            const double xa1 = box_node(fap1, level - 1, tb.z[fatp1]);
+#pragma unroll
+            for (int tp2 = 0; tp2 < Q; ++tp2) {
+                const XP xp = make_xp_sc(ph, xa1, box_node(fap2, level - 1, tb.z[tp2]), sp[fb][0][fatp1],
+                                         cp[fb][0][fatp1], sp[fb][1][tp2], cp[fb][1][tp2]);
+                Ep[tp2] = cis<T>(r0c[fb][c1] * phase_dir(xp, ct0[fb][c2], st0[fb][c2]));
+            }
+        }
+        if (sactive) {
+#pragma unroll
+            for (int o = 0; o < 2 * NG; ++o) {
+                const double G0 = remod_phase(o >> 1, o & 1, 0), G1 = remod_phase(o >> 1, o & 1, 1);
+                E2[0][o] = cis<T>(r0c[sb][0] * G0);
+                E2[1][o] = cis<T>(r0c[sb][0] * G1);
+                E2[2][o] = cis<T>(r0c[sb][1] * G0);
+                E2[3][o] = cis<T>(r0c[sb][1] * G1);
+            }
+        }
         // inputs of the first-pass row, loaded one right-hand side ahead, during
         // the second pass (issuing it before the first pass measured slower)
         cpx<T> nx[Q];
-        auto load_row = [&](int r) {
+        auto load_row = [&](int r) __attribute__((always_inline)) {
             const cpx<T> *src = win + r * plane + (fblk * 4 + fac) * QQ + fatp1 * Q;
 #pragma unroll
             for (int tp2 = 0; tp2 < Q; ++tp2) nx[tp2] = src[tp2];
         };
         if (factive) load_row(0);
         for (int r = 0; r < nrhs; ++r) {
-            // first pass with the prefactor: Y[a2][c][t'1][t2] =
-            //   sum_t'2 M_a2[t'2][t2] conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t'
+            opaque_sgpr(SAg);
+            STg = SAg + 2 * QQ;
+            ATg = SAg + 3 * QQ;
             if (factive) {
-                cpx<T> acc[Q];
+                cpx<T> vv[Q];
 #pragma unroll
-                for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
-#pragma unroll
-                for (int tp2 = 0; tp2 < Q; ++tp2) {
-                    const cpx<T> vv = cmulc(nx[tp2], Ep[tp2]);
-#pragma unroll
-                    for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Mg[(fa2 * Q + tp2) * Q + tt], vv);
-                }
-#pragma unroll
-                for (int tt = 0; tt < Q; ++tt) Y[fb][fa2][fac][fatp1 * Q + tt] = acc[tt];
+                for (int tp2 = 0; tp2 < Q; ++tp2) vv[tp2] = cmulc(nx[tp2], Ep[tp2]);
+                first_pass(vv);
             }
             lds_barrier();
             if (factive && r + 1 < nrhs) load_row(r + 1);
-            if (active) {
-                cpx<T> out[H1];
+            if (sactive) with_uniform<0, 4>(sg, [&](auto gc) __attribute__((always_inline)) {
+                cpx<T> out[2 * NG];
 #pragma unroll
-                for (int kk = 0; kk < H1; ++kk) out[kk] = {(T)0, (T)0};
+                for (int o = 0; o < 2 * NG; ++o) out[o] = {(T)0, (T)0};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    cpx<T> col[Q];
+                    cpx<T> z[2 * NG];
+                    second_pass_c(gc, c, z);
 #pragma unroll
-                    for (int tp1 = 0; tp1 < Q; ++tp1) col[tp1] = Y[bbl][j2][c][tp1 * Q + t2];
-#pragma unroll
-                    for (int kk = 0; kk < H1; ++kk) {
-                        const int t1 = min(h * H1 + kk, Q - 1);
-                        cpx<T> z = {(T)0, (T)0};
-#pragma unroll
-                        for (int tp1 = 0; tp1 < Q; ++tp1) crfma(z, Ms[j1][tp1][t1], col[tp1]);
-                        cfma(out[kk], E2[c][kk], z);
-                    }
+                    for (int o = 0; o < 2 * NG; ++o) cfma(out[o], E2[c][o], z[o]);
                 }
-                cpx<T> *dst = wout + r * plane + ((size_t)(4 * mAp + jj) * nBl + mB) * QQ;
-#pragma unroll
-                for (int kk = 0; kk < H1; ++kk) {
-                    const int t1 = h * H1 + kk;
-                    if (t1 < Q) dst[t1 * Q + t2] = out[kk];
-                }
-            }
+                store_outputs(gc, out, r * plane);
+            });
             lds_barrier();
         }
         return;
@@ -550,63 +650,49 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
     // one right-hand side: prefactor conj E(x^{A_p}_t', p0(B_c)) delta^{A_p B_c}_t'
     // once per row (c, t'1)
     if (active && rr < 4 * Q) {
+        const int pc = rr / Q, ptp1 = rr - pc * Q;
+        const int c2 = pc & 1, c1 = pc >> 1;
         const cpx<T> *src = win + (blk * 4 + pc) * QQ + ptp1 * Q;
 #pragma unroll
-        for (int tp2 = 0; tp2 < Q; ++tp2) v[bbl][pc][ptp1 * Q + tp2] = cmulc(src[tp2], pre_exp(tp2));
-    }
-    lds_barrier();
-    // first pass (second dimension): Y[a2][c][t'1][t2] = sum_t'2 M_a2[t'2][t2] v[c][t'1][t'2]
-    if (active) {
-        cpx<T> acc[Q];
-#pragma unroll
-        for (int t = 0; t < Q; ++t) acc[t] = {(T)0, (T)0};
-#pragma unroll
         for (int tp2 = 0; tp2 < Q; ++tp2) {
-            const cpx<T> vv = v[bbl][ac][atp1 * Q + tp2];
-#pragma unroll
-            for (int tt = 0; tt < Q; ++tt) crfma(acc[tt], Ms[a2c][tp2][tt], vv);
+            const XP xp = make_xp_sc(ph, box_node(ap1, level - 1, tb.z[ptp1]),
+                                     box_node(ap2, level - 1, tb.z[tp2]), sp[bbl][0][ptp1], cp[bbl][0][ptp1],
+                                     sp[bbl][1][tp2], cp[bbl][1][tp2]);
+            v[bbl][pc][ptp1 * Q + tp2] =
+                cmulc(src[tp2], cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2])));
         }
-#pragma unroll
-        for (int tt = 0; tt < Q; ++tt) Y[bbl][a2c][ac][atp1 * Q + tt] = acc[tt];
     }
     lds_barrier();
-    // second pass (first dimension), remodulation E(x^A_t, p0(B_c)), sum over c
-    if (active) {
-        cpx<T> out[H1];
-        const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
-        double G0[H1], G1[H1];
-        const double xb2 = box_node(a2, level, tb.z[t2]);
+    if (factive) {
+        cpx<T> vv[Q];
 #pragma unroll
-        for (int kk = 0; kk < H1; ++kk) {
-            const int t1 = min(h * H1 + kk, Q - 1);
-            const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), xb2, sj[bbl][0][j1][t1],
-                                     cj[bbl][0][j1][t1], sj[bbl][1][j2][t2], cj[bbl][1][j2][t2]);
-            G0[kk] = phase_dir(xp, ct0[bbl][0], st0[bbl][0]);
-            G1[kk] = phase_dir(xp, ct0[bbl][1], st0[bbl][1]);
-            out[kk] = {(T)0, (T)0};
+        for (int tp2 = 0; tp2 < Q; ++tp2) vv[tp2] = v[fb][fac][fatp1 * Q + tp2];
+        first_pass(vv);
+    }
+    lds_barrier();
+    // second pass, remodulation E(x^A_t, p0(B_c)), sum over c
+    if (sactive) {
+        double G0[2 * NG], G1[2 * NG];
+#pragma unroll
+        for (int o = 0; o < 2 * NG; ++o) {
+            G0[o] = remod_phase(o >> 1, o & 1, 0);
+            G1[o] = remod_phase(o >> 1, o & 1, 1);
         }
-#pragma unroll 1
-        for (int c = 0; c < 4; ++c) {
-            const int c1 = c >> 1, c2 = c & 1;
-            cpx<T> col[Q];
+        cpx<T> out[2 * NG];
 #pragma unroll
-            for (int tp1 = 0; tp1 < Q; ++tp1) col[tp1] = Y[bbl][j2][c][tp1 * Q + t2];
-            const double rho = r0c[bbl][c1];
+        for (int o = 0; o < 2 * NG; ++o) out[o] = {(T)0, (T)0};
+        with_uniform<0, 4>(sg, [&](auto gc) __attribute__((always_inline)) {
 #pragma unroll
-            for (int kk = 0; kk < H1; ++kk) {
-                const int t1 = min(h * H1 + kk, Q - 1);
-                cpx<T> z = {(T)0, (T)0};
+            for (int c = 0; c < 4; ++c) {
+                const int c1 = c >> 1, c2 = c & 1;
+                cpx<T> z[2 * NG];
+                second_pass_c(gc, c, z);
+                const double rho = r0c[sb][c1];
 #pragma unroll
-                for (int tp1 = 0; tp1 < Q; ++tp1) crfma(z, Ms[j1][tp1][t1], col[tp1]);
-                cfma(out[kk], cis<T>(rho * (c2 ? G1[kk] : G0[kk])), z);
+                for (int o = 0; o < 2 * NG; ++o) cfma(out[o], cis<T>(rho * (c2 ? G1[o] : G0[o])), z[o]);
             }
-        }
-        cpx<T> *dst = wout + ((size_t)(4 * mAp + jj) * nBl + mB) * QQ;
-#pragma unroll
-        for (int kk = 0; kk < H1; ++kk) {
-            const int t1 = h * H1 + kk;
-            if (t1 < Q) dst[t1 * Q + t2] = out[kk];
-        }
+            store_outputs(gc, out, 0);
+        });
     }
 }
 

@@ -352,12 +352,27 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
             for (int j = 0; j < q; ++j) M[(c * q + t) * q + j] = lagrange(z, t, (z[j] + c - 0.5) / 2.0);
     for (int jj = 0; jj < m; ++jj)
         for (int t = 0; t < q; ++t) Tt[jj * q + t] = lagrange(z, t, (double)jj / m - 0.5);
-    std::vector<float> Mf(M.begin(), M.end()), Ttf(Tt.begin(), Tt.end());
+    // symmetric and antisymmetric halves of M_0 (the kernels use M_1 = J M_0 J)
+    std::vector<double> SA(4 * q * q, 0.0);
+    const int hq = q / 2;
+    for (int n = 0; n < q; ++n)
+        for (int m = 0; m < q; ++m) {
+            SA[(0 * q + n) * q + m] = 0.5 * (M[n * q + m] + M[(q - 1 - n) * q + m]);
+            SA[(1 * q + n) * q + m] = 0.5 * (M[n * q + m] - M[(q - 1 - n) * q + m]);
+            if (m < hq) {
+                SA[(2 * q + n) * q + m] = 0.5 * (M[m * q + n] + M[(q - 1 - m) * q + n]);
+                SA[(3 * q + n) * q + m] = 0.5 * (M[m * q + n] - M[(q - 1 - m) * q + n]);
+            } else if (m == hq && (q & 1)) {
+                SA[(2 * q + n) * q + m] = M[m * q + n];
+            }
+        }
+    std::vector<float> Mf(M.begin(), M.end()), Ttf(Tt.begin(), Tt.end()), SAf(SA.begin(), SA.end());
 
-    // table blob: z | lam | M | Tt | Mf | Ttf  (256-byte aligned pieces)
+    // table blob: z | lam | M | Tt | Mf | Ttf | SA | SAf  (256-byte aligned pieces)
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t oz = 0, olam = al(oz + q * 8), oM = al(olam + q * 8), oT = al(oM + M.size() * 8),
-                 oMf = al(oT + Tt.size() * 8), oTf = al(oMf + Mf.size() * 4), tbytes = al(oTf + Ttf.size() * 4);
+                 oMf = al(oT + Tt.size() * 8), oTf = al(oMf + Mf.size() * 4), oSA = al(oTf + Ttf.size() * 4),
+                 oSAf = al(oSA + SA.size() * 8), tbytes = al(oSAf + SAf.size() * 4);
     std::vector<unsigned char> blob(tbytes, 0);
     memcpy(&blob[oz], z.data(), q * 8);
     memcpy(&blob[olam], lam.data(), q * 8);
@@ -365,6 +380,8 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     memcpy(&blob[oT], Tt.data(), Tt.size() * 8);
     memcpy(&blob[oMf], Mf.data(), Mf.size() * 4);
     memcpy(&blob[oTf], Ttf.data(), Ttf.size() * 4);
+    memcpy(&blob[oSA], SA.data(), SA.size() * 8);
+    memcpy(&blob[oSAf], SAf.data(), SAf.size() * 4);
 
     // ---- device memory
     const size_t csize = dtype == FIO_C128 ? 16 : 8;
@@ -395,6 +412,8 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     p->tb.Tt = (const double *)(base + oT);
     p->tb.Mf = (const float *)(base + oMf);
     p->tb.Ttf = (const float *)(base + oTf);
+    p->tb.SA = (const double *)(base + oSA);
+    p->tb.SAf = (const float *)(base + oSAf);
     p->geom.N = N;
     p->geom.L = L;
     p->geom.q = q;
