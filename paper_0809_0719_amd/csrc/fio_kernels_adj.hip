@@ -115,7 +115,10 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
     static_assert(BPW * 4 * Q <= NT / 2, "second pass: a block's columns fit a half workgroup");
     constexpr int H1 = (Q + 1) / 2, H = Q / 2;
     constexpr int NK = (H1 + 1) / 2;                // row pairs per second-pass thread
-    __shared__ cpx<T> Y[BPW][2][4][QQ];             // [j1][c][t1][t'2]
+    constexpr int YC = QQ + pad_xadj_c<T, Q>(), YJ = 4 * YC + pad_xadj_j<T, Q>();
+    __shared__ cpx<T> Y[BPW][2][YJ];                // [j1][c][t1][t'2] (+ bank padding)
+    constexpr int NE = BPW * 4 * QQ;                // the workgroup's inputs: BPW blocks x 4 outputs j
+    __shared__ cpx<T> xin[stage_len<NE>()];
     __shared__ double sp[BPW][2][Q], cp[BPW][2][Q];
     __shared__ double sj[BPW][2][2][Q], cj[BPW][2][2][Q];
     __shared__ double r0c[BPW][2], ct0[BPW][2], st0[BPW][2];
@@ -199,23 +202,22 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
             E2[2 * k + 1] = pre_exp(Q - 1 - n);
         }
     }
-    // inputs of the thread's two rows, loaded one right-hand side ahead
-    cpx<T> nx[2][Q];
-    auto load_rows = [&](int r) __attribute__((always_inline)) {
-#pragma unroll
-        for (int j2 = 0; j2 < 2; ++j2) {
-            const cpx<T> *src = win + r * plane + ((size_t)(4 * mAp + 2 * j1 + j2) * nBl + mB) * QQ + t1 * Q;
-#pragma unroll
-            for (int t2 = 0; t2 < Q; ++t2) nx[j2][t2] = src[t2];
-        }
+    // inputs staged through LDS by coalesced loads, one right-hand side ahead:
+    // piece (block b, output j) is QQ values at ((4 A_p + j) nBl + B) QQ
+    cpx<T> stv[stage_per<NE>()];
+    auto piece = [&](int e) __attribute__((always_inline)) {
+        const int b = e / (4 * QQ), rem = e - b * (4 * QQ), jj = rem / QQ, o = rem - jj * QQ;
+        const size_t pb = (size_t)blockIdx.x * BPW + b;
+        return pb < nblk ? ((4 * (pb >> (2 * lB)) + jj) * nBl + (pb & (nBl - 1))) * QQ + o : (size_t)0;
     };
-    constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
-    if (PF && active) load_rows(0);
+    stage_fetch<NE>(stv, win, piece);
+    stage_put<NE>(stv, xin);
+    lds_barrier();
+    const cpx<T> *const in0 = &xin[(bbl * 4 + 2 * j1) * QQ + t1 * Q];  // row t1 of child (j1, 0); + QQ: (j1, 1)
     cpx<T> *const dst0 = wout + (sblk * 4 + sc) * QQ;
     for (int r = 0; r < (HOIST ? nrhs : 1); ++r) {
         opaque_sgpr(SAg);
         if (active) {
-            if (!PF) load_rows(r);
             // a = v_0 + J v_1, b = v_0 - J v_1 with v_j2 = conj E . delta of child (j1, j2)
             cpx<T> P[H1], D[H > 0 ? H : 1];
 #pragma unroll
@@ -224,8 +226,8 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
             for (int n = 0; n < H; ++n) D[n] = {(T)0, (T)0};
 #pragma unroll
             for (int m = 0; m < Q; ++m) {
-                const cpx<T> v0 = cmulc(nx[0][m], HOIST ? E1[0][m] : row_exp(0, m));
-                const cpx<T> v1 = cmulc(nx[1][Q - 1 - m], HOIST ? E1[1][Q - 1 - m] : row_exp(1, Q - 1 - m));
+                const cpx<T> v0 = cmulc(in0[m], HOIST ? E1[0][m] : row_exp(0, m));
+                const cpx<T> v1 = cmulc(in0[QQ + Q - 1 - m], HOIST ? E1[1][Q - 1 - m] : row_exp(1, Q - 1 - m));
                 const cpx<T> av = {v0.re + v1.re, v0.im + v1.im};
                 const cpx<T> bv = {v0.re - v1.re, v0.im - v1.im};
 #pragma unroll
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
 #pragma unroll
                 for (int n = 0; n < H; ++n) crfma(D[n], SAg[QQ + n * Q + m], bv);
             }
-            cpx<T> *wr = &Y[bbl][j1][fc][t1 * Q];
+            cpx<T> *wr = &Y[bbl][j1][fc * YC + t1 * Q];
 #pragma unroll
             for (int n = 0; n < H; ++n) {
                 wr[n] = {P[n].re + D[n].re, P[n].im + D[n].im};
@@ -242,8 +244,10 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
             if constexpr (Q & 1) wr[H] = P[H];
         }
         lds_barrier();
-        // the next right-hand side's rows are loaded during the second pass
-        if (PF && active && r + 1 < nrhs) load_rows(r + 1);
+        // the next right-hand side's inputs are loaded during the second pass
+        // (unconditionally: the last one refetches the last right-hand side,
+        // which keeps the staged values in registers)
+        if (HOIST) stage_fetch<NE>(stv, win + (size_t)min(r + 1, nrhs - 1) * plane, piece);
         if (sactive) with_uniform<0, 2>(h, [&](auto hc) __attribute__((always_inline)) {
             constexpr int hh = decltype(hc)::value;
             cpx<T> Pn[NK], Dn[NK];
@@ -251,7 +255,8 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
             for (int k = 0; k < NK; ++k) Pn[k] = Dn[k] = {(T)0, (T)0};
 #pragma unroll
             for (int p = 0; p < Q; ++p) {
-                const cpx<T> x0 = Y[sb][0][sc][p * Q + tp2], x1 = Y[sb][1][sc][(Q - 1 - p) * Q + tp2];
+                const cpx<T> x0 = Y[sb][0][sc * YC + p * Q + tp2];
+                const cpx<T> x1 = Y[sb][1][sc * YC + (Q - 1 - p) * Q + tp2];
                 const cpx<T> av = {x0.re + x1.re, x0.im + x1.im};
                 const cpx<T> bv = {x0.re - x1.re, x0.im - x1.im};
 #pragma unroll
@@ -277,6 +282,7 @@ __global__ __launch_bounds__(NT) void k_xlevel_adj(Geom g, PhaseDev ph, Tables t
                 }
             }
         });
+        if (HOIST) stage_put<NE>(stv, xin);
         lds_barrier();
     }
 }
@@ -453,7 +459,10 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
     __shared__ double rc[BPW][2 * Q], ctc[BPW][2 * Q], stc[BPW][2 * Q];
     __shared__ double rb[BPW][Q], ctb[BPW][Q], stb[BPW][Q];
     __shared__ double Gc[BPW][4][2 * Q], Gb[BPW][4][Q];
-    __shared__ cpx<T> Y[BPW][2][4][QQ];   // [c2][j][t1][t'2] (c2 outside j: fewer LDS bank conflicts)
+    constexpr int YA = 4 * QQ + pad_sum_out<T, Q>();
+    __shared__ cpx<T> Y[BPW][2][YA];      // [c2][j][t1][t'2] (+ bank padding)
+    constexpr int NE = BPW * 4 * QQ;      // the workgroup's inputs: BPW blocks x 4 outputs j
+    __shared__ cpx<T> xin[stage_len<NE>()];
 
     const int tid = threadIdx.x;
     const int bbl = tid / TPB, r = tid - bbl * TPB;
@@ -539,8 +548,8 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
                 for (int m = 0; m < H1; ++m) crfma(P, STg[n * Q + m], sv[m]);
 #pragma unroll
                 for (int m = 0; m < H; ++m) crfma(D, ATg[n * Q + m], dv[m]);
-                Y[fb][0][fj][t1 * Q + n] = {P.re + D.re, P.im + D.im};
-                Y[fb][1][fj][t1 * Q + Q - 1 - n] = {P.re - D.re, P.im - D.im};
+                Y[fb][0][fj * QQ + t1 * Q + n] = {P.re + D.re, P.im + D.im};
+                Y[fb][1][fj * QQ + t1 * Q + Q - 1 - n] = {P.re - D.re, P.im - D.im};
             }
         }
         });
@@ -549,7 +558,7 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
     auto second_pass_j = [&](auto gc, int jj, cpx<T> (&z)[2 * NG]) __attribute__((always_inline)) {
         constexpr int gg = decltype(gc)::value;
         cpx<T> sv[H1], dv[H > 0 ? H : 1];
-        const cpx<T> *col = &Y[sb][sc2][jj][tp2];
+        const cpx<T> *col = &Y[sb][sc2][jj * QQ + tp2];
 #pragma unroll
         for (int m = 0; m < H; ++m) {
             const cpx<T> x0 = col[m * Q], x1 = col[(Q - 1 - m) * Q];
@@ -586,30 +595,33 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
             for (int o = 0; o < 2 * NG; ++o) E2[jj][o] = cis<T>(rc[sb][(o & 1) * Q + out_row(o)] * G);
         }
     }
-    // inputs of the thread's row, loaded one right-hand side ahead
-    cpx<T> nx[Q];
-    auto load_row = [&](int ri) __attribute__((always_inline)) {
-        const cpx<T> *src = win + ri * plane + ((size_t)(4 * fmAp + fj) * nBl + fmB) * QQ + t1 * Q;
-#pragma unroll
-        for (int t2 = 0; t2 < Q; ++t2) nx[t2] = src[t2];
+    // inputs staged through LDS by coalesced loads, one right-hand side ahead:
+    // piece (block b, output j) is QQ values at ((4 A_p + j) nBl + B) QQ
+    cpx<T> stv[stage_per<NE>()];
+    auto piece = [&](int e) __attribute__((always_inline)) {
+        const int b = e / (4 * QQ), rem = e - b * (4 * QQ), jj = rem / QQ, o = rem - jj * QQ;
+        const size_t pb = (size_t)blockIdx.x * BPW + b;
+        return pb < nblk ? ((4 * (pb >> (2 * lB)) + jj) * nBl + (pb & (nBl - 1))) * QQ + o : (size_t)0;
     };
-    constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
-    if (PF && factive) load_row(0);
+    stage_fetch<NE>(stv, win, piece);
+    stage_put<NE>(stv, xin);
+    lds_barrier();
+    const cpx<T> *const in = &xin[(fb * 4 + fj) * QQ + t1 * Q];
     for (int ri = 0; ri < (HOIST ? nrhs : 1); ++ri) {
         opaque_sgpr(SAg);
         STg = SAg + 2 * QQ;
         ATg = SAg + 3 * QQ;
         if (factive) {
-            if (!PF) load_row(ri);
             cpx<T> gv[Q];
 #pragma unroll
-            for (int t2 = 0; t2 < Q; ++t2) gv[t2] = cmul(nx[t2], HOIST ? E1[t2] : cis<T>(rhoB * Gb[fb][fj][t2]));
+            for (int t2 = 0; t2 < Q; ++t2) gv[t2] = cmul(in[t2], HOIST ? E1[t2] : cis<T>(rhoB * Gb[fb][fj][t2]));
             first_pass(gv);
         }
         lds_barrier();
-        // the next right-hand side's row is loaded during the (longer) second
-        // pass (issuing it before the first pass measured slower)
-        if (PF && factive && ri + 1 < nrhs) load_row(ri + 1);
+        // the next right-hand side's inputs are loaded during the second pass
+        // (unconditionally: the last one refetches the last right-hand side,
+        // which keeps the staged values in registers)
+        if (HOIST) stage_fetch<NE>(stv, win + (size_t)min(ri + 1, nrhs - 1) * plane, piece);
         if (sactive) with_uniform<0, 4>(sg, [&](auto gc) __attribute__((always_inline)) {
             constexpr int gg = decltype(gc)::value;
             cpx<T> acc[2 * NG];
@@ -638,6 +650,7 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
                 }
             }
         });
+        if (HOIST) stage_put<NE>(stv, xin);
         lds_barrier();
     }
 }

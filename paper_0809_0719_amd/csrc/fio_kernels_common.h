@@ -87,6 +87,68 @@ template <typename T>
 constexpr int swadj_rc() { return sizeof(T) == 4 ? 4 : 2; }
 
 
+// Padding (complex64 elements) of the level kernels' LDS buffers, chosen per
+// q with a model of the LDS banks (32 banks of 4 bytes, 64-bit accesses
+// served 16 lanes at a time) over both passes' lane-to-address maps:
+//   pad_sum_out: after each child's 4 q^2 first-pass rows in the kernels
+//     whose passes feed one input to two children (x-level, p-level^H);
+//   pad_plevel: after each output's 2 q^2 first-pass rows of the p-level;
+//   pad_xadj_c, pad_xadj_j: after each q^2 block of c, and after each j1
+//     block, of the x-level^H.
+// Complex128 buffers are not padded.
+template <typename T, int Q>
+constexpr int pad_sum_out() {
+    constexpr int t[17] = {0, 0, 0, 15, 4, 1, 6, 3, 8, 5, 10, 7, 12, 9, 14, 11, 0};
+    return sizeof(T) == 4 ? t[Q] : 0;
+}
+template <typename T, int Q>
+constexpr int pad_plevel() {
+    constexpr int t[17] = {0, 0, 0, 0, 2, 3, 14, 5, 8, 7, 2, 9, 12, 11, 6, 13, 0};
+    return sizeof(T) == 4 ? t[Q] : 0;
+}
+template <typename T, int Q>
+constexpr int pad_xadj_c() {
+    constexpr int t[17] = {0, 0, 0, 10, 3, 0, 2, 6, 1, 8, 6, 2, 12, 4, 10, 14, 0};
+    return sizeof(T) == 4 ? t[Q] : 0;
+}
+template <typename T, int Q>
+constexpr int pad_xadj_j() {
+    constexpr int t[17] = {0, 0, 0, 2, 0, 0, 4, 10, 0, 14, 4, 10, 0, 6, 4, 2, 0};
+    return sizeof(T) == 4 ? t[Q] : 0;
+}
+
+// Coalesced staging of a workgroup's input weights for one right-hand side:
+// NE complex values made of pieces of consecutive values of a weight plane
+// (piece(e) gives the plane offset of staged element e), copied through
+// registers into an LDS buffer of stage_len<NE>() values in element order.
+// Thread tid moves elements tid, tid + NT, ...: consecutive lanes read
+// consecutive addresses, so a load instruction reads 64 adjacent values
+// instead of 64 rows q values apart.  Elements past NE read element 0 of the
+// plane and land in the buffer's tail, which nothing reads.  The offsets are
+// recomputed per fetch (a few integer operations) rather than held in
+// registers for the whole kernel.
+template <int NE>
+constexpr int stage_len() {
+    return ((NE + NT - 1) / NT) * NT;
+}
+template <int NE>
+constexpr int stage_per() {
+    return (NE + NT - 1) / NT;
+}
+template <int NE, typename T, typename F>
+__device__ __forceinline__ void stage_fetch(cpx<T> (&v)[stage_per<NE>()], const cpx<T> *plane, F &&piece) {
+#pragma unroll
+    for (int k = 0; k < stage_per<NE>(); ++k) {
+        const int e = (int)threadIdx.x + k * NT;
+        v[k] = plane[e < NE ? piece(e) : (size_t)0];
+    }
+}
+template <int NE, typename T>
+__device__ __forceinline__ void stage_put(const cpx<T> (&v)[stage_per<NE>()], cpx<T> *stage) {
+#pragma unroll
+    for (int k = 0; k < stage_per<NE>(); ++k) stage[threadIdx.x + k * NT] = v[k];
+}
+
 // Grids of more than 2^32 / NT workgroups (the work-item limit of one grid
 // dimension): the workgroups are laid out over (x, y) with x at most 2^16,
 // and kernels take their linear index.  Workgroups past the count the

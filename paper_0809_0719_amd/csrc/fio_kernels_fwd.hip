@@ -146,7 +146,10 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
     __shared__ double rc[BPW][2 * Q], ctc[BPW][2 * Q], stc[BPW][2 * Q];  // child nodes: rho(c1,t'), theta(c2,t')
     __shared__ double rb[BPW][Q], ctb[BPW][Q], stb[BPW][Q];              // B's nodes
     __shared__ double Gc[BPW][4][2 * Q], Gb[BPW][4][Q];
-    __shared__ cpx<T> W[BPW][4][2 * QQ];  // first-pass rows [c1][t'1][t2]
+    constexpr int WJ = 2 * QQ + pad_plevel<T, Q>();
+    __shared__ cpx<T> W[BPW][4][WJ];      // first-pass rows [c1][t'1][t2] (+ bank padding)
+    constexpr int NE = BPW * 4 * QQ;      // the workgroup's inputs: BPW blocks x 4 children, contiguous
+    __shared__ cpx<T> xin[stage_len<NE>()];
 
     const int tid = threadIdx.x;
     const int bbl = tid / TPB, r = tid - bbl * TPB;
@@ -156,6 +159,11 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
     const int lB = g.L - level;
     const size_t nBl = (size_t)1 << (2 * lB);
     cptr<T> SAg = to_constant(pick_SA<T>(tb));
+    // inputs staged through LDS one right-hand side ahead
+    cpx<T> stv[stage_per<NE>()];
+    auto piece = [&](int e) __attribute__((always_inline)) {
+        return (size_t)blockIdx.x * BPW + e / (4 * QQ) < nblk ? (size_t)blockIdx.x * NE + e : (size_t)0;
+    };
 
     uint32_t mB = 0, mAp = 0;
     int b1 = 0, b2 = 0, ap1 = 0, ap2 = 0;
@@ -182,12 +190,14 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
         }
     }
     lds_barrier();
+    stage_fetch<NE>(stv, win, piece);  // after the node tables (their sine/cosine calls would save it to scratch)
     const int a1 = 2 * ap1 + (j >> 1), a2 = 2 * ap2 + (j & 1);
     if (active) {
         const XP xp = make_xp(ph, box_centre(a1, level), box_centre(a2, level));
         Gc[bbl][j][rr] = phase_dir(xp, ctc[bbl][rr], stc[bbl][rr]);
         if (rr < Q) Gb[bbl][j][rr] = phase_dir(xp, ctb[bbl][rr], stb[bbl][rr]);
     }
+    stage_put<NE>(stv, xin);
     lds_barrier();
     // first-pass row (c1, t'1)
     const int c1 = rr / Q, tp1 = rr - c1 * Q;
@@ -216,24 +226,11 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
             }
         }
     }
-    // inputs of the thread's row, loaded one right-hand side ahead
-    cpx<T> nx[2 * Q];
-    auto load_row = [&](int r) __attribute__((always_inline)) {
-#pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2) {
-            const cpx<T> *src = win + r * plane + (blk * 4 + 2 * c1 + c2) * QQ + tp1 * Q;
-#pragma unroll
-            for (int tp2 = 0; tp2 < Q; ++tp2) nx[c2 * Q + tp2] = src[tp2];
-        }
-    };
-    constexpr bool PF = HOIST && !(sizeof(T) == 8 && Q > 10);  // prefetch unless it spills
-    if (PF && active) load_row(0);
     cpx<T> *const dst0 = wout + ((size_t)(4 * (sblk >> (2 * lB)) + sj) * nBl + (sblk & (nBl - 1))) * QQ;
+    const cpx<T> *const in = &xin[(bbl * 4 + 2 * c1) * QQ + tp1 * Q];  // row of child (c1, 0); + QQ: (c1, 1)
     for (int r = 0; r < (HOIST ? nrhs : 1); ++r) {
         opaque_sgpr(SAg);
         if (active) {
-            if (!PF) load_row(r);
-            const cpx<T>(&in)[2 * Q] = nx;
             // first pass: row (c1, t'1); a = v_0 + J v_1, b = v_0 - J v_1
             cpx<T> P[H1], D[H > 0 ? H : 1];
 #pragma unroll
@@ -245,7 +242,7 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
                 const cpx<T> e0 = HOIST ? Ea[m] : cis<T>(rhoA * Gc[bbl][j][m]);
                 const cpx<T> e1 = HOIST ? Ea[2 * Q - 1 - m] : cis<T>(rhoA * Gc[bbl][j][2 * Q - 1 - m]);
                 const cpx<T> v0 = cmul(e0, in[m]);
-                const cpx<T> v1 = cmul(e1, in[2 * Q - 1 - m]);
+                const cpx<T> v1 = cmul(e1, in[QQ + Q - 1 - m]);
                 const cpx<T> av = {v0.re + v1.re, v0.im + v1.im};
                 const cpx<T> bv = {v0.re - v1.re, v0.im - v1.im};
 #pragma unroll
@@ -262,9 +259,11 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
             if constexpr (Q & 1) wr[H] = P[H];
         }
         lds_barrier();
-        // the next right-hand side's row is loaded during the second pass, once
-        // the first pass has consumed this one
-        if (PF && active && r + 1 < nrhs) load_row(r + 1);
+        // the next right-hand side's inputs are loaded during the second pass
+        // and staged once it is done (the first pass has consumed this one's)
+        // (unconditionally: the last one refetches the last right-hand side,
+        // which keeps the staged values in registers rather than in scratch)
+        if (HOIST) stage_fetch<NE>(stv, win + (size_t)min(r + 1, nrhs - 1) * plane, piece);
         if (sactive) with_uniform<0, 2>(h, [&](auto hc) __attribute__((always_inline)) {
             constexpr int hh = decltype(hc)::value;
             // second pass: column st2 over c1 (a = W_0 + J W_1, b = W_0 - J W_1),
@@ -302,6 +301,7 @@ __global__ __launch_bounds__(NT) void k_plevel(Geom g, PhaseDev ph, Tables tb, i
                 }
             }
         });
+        if (HOIST) stage_put<NE>(stv, xin);
         lds_barrier();
     }
 }
@@ -444,8 +444,10 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
     static_assert(BPW * 4 * Q <= NT / 2 && BPW * 2 * Q <= 64, "pass layouts fit the workgroup");
     constexpr int H1 = (Q + 1) / 2, H = Q / 2;
     constexpr int NG = (Q + 3) / 4;                 // second-pass rows per thread
-    __shared__ cpx<T> v[BPW][4][QQ];                // prefactored inputs [c][t'1][t'2] (one RHS)
-    __shared__ cpx<T> Y[BPW][2][4][QQ];             // first pass [a2][c][t'1][t2]
+    constexpr int NE = BPW * 4 * QQ;                // the workgroup's inputs: BPW blocks x 4 children, contiguous
+    __shared__ cpx<T> xin[stage_len<NE>()];         // inputs (several RHS) or prefactored inputs (one)
+    constexpr int YA = 4 * QQ + pad_sum_out<T, Q>();
+    __shared__ cpx<T> Y[BPW][2][YA];                // first pass [a2][c][t'1][t2] (+ bank padding)
     __shared__ double sp[BPW][2][Q], cp[BPW][2][Q];        // sin/cos(2 pi x) at A_p's nodes, per dim
     __shared__ double sj[BPW][2][2][Q], cj[BPW][2][2][Q];  // at the children's nodes [dim][a][t]
     __shared__ double r0c[BPW][2], ct0[BPW][2], st0[BPW][2];
@@ -539,8 +541,8 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
                 for (int m = 0; m < H1; ++m) crfma(P, STg[n * Q + m], sv[m]);
 #pragma unroll
                 for (int m = 0; m < H; ++m) crfma(D, ATg[n * Q + m], dv[m]);
-                Y[fb][0][fac][fatp1 * Q + n] = {P.re + D.re, P.im + D.im};
-                Y[fb][1][fac][fatp1 * Q + Q - 1 - n] = {P.re - D.re, P.im - D.im};
+                Y[fb][0][fac * QQ + fatp1 * Q + n] = {P.re + D.re, P.im + D.im};
+                Y[fb][1][fac * QQ + fatp1 * Q + Q - 1 - n] = {P.re - D.re, P.im - D.im};
             }
         }
         });
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
     auto second_pass_c = [&](auto gc, int c, cpx<T> (&z)[2 * NG]) __attribute__((always_inline)) {
         constexpr int gg = decltype(gc)::value;
         cpx<T> sv[H1], dv[H > 0 ? H : 1];
-        const cpx<T> *col = &Y[sb][sj2][c][st2];
+        const cpx<T> *col = &Y[sb][sj2][c * QQ + st2];
 #pragma unroll
         for (int m = 0; m < H; ++m) {
             const cpx<T> x0 = col[m * Q], x1 = col[(Q - 1 - m) * Q];
@@ -585,6 +587,11 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
     };
 
     if constexpr (HOIST) {
+        cpx<T> stv[stage_per<NE>()];
+        auto piece = [&](int e) __attribute__((always_inline)) {
+            return (size_t)blockIdx.x * BPW + e / (4 * QQ) < nblk ? (size_t)blockIdx.x * NE + e : (size_t)0;
+        };
+        stage_fetch<NE>(stv, win, piece);
         // exponentials shared by all right-hand sides: the prefactor of the
         // first-pass row (every first-pass thread applies its own) and the
         // remodulation of the second-pass outputs
@@ -609,15 +616,11 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
                 E2[3][o] = cis<T>(r0c[sb][1] * G1);
             }
         }
-        // inputs of the first-pass row, loaded one right-hand side ahead, during
-        // the second pass (issuing it before the first pass measured slower)
-        cpx<T> nx[Q];
-        auto load_row = [&](int r) __attribute__((always_inline)) {
-            const cpx<T> *src = win + r * plane + (fblk * 4 + fac) * QQ + fatp1 * Q;
-#pragma unroll
-            for (int tp2 = 0; tp2 < Q; ++tp2) nx[tp2] = src[tp2];
-        };
-        if (factive) load_row(0);
+        // inputs staged through LDS by coalesced loads, one right-hand side
+        // ahead: loaded during the second pass, staged once it is done
+        stage_put<NE>(stv, xin);
+        lds_barrier();
+        const cpx<T> *const in = &xin[(fb * 4 + fac) * QQ + fatp1 * Q];
         for (int r = 0; r < nrhs; ++r) {
             opaque_sgpr(SAg);
             STg = SAg + 2 * QQ;
@@ -625,11 +628,13 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
             if (factive) {
                 cpx<T> vv[Q];
 #pragma unroll
-                for (int tp2 = 0; tp2 < Q; ++tp2) vv[tp2] = cmulc(nx[tp2], Ep[tp2]);
+                for (int tp2 = 0; tp2 < Q; ++tp2) vv[tp2] = cmulc(in[tp2], Ep[tp2]);
                 first_pass(vv);
             }
             lds_barrier();
-            if (factive && r + 1 < nrhs) load_row(r + 1);
+            // (the last one refetches the last right-hand side: unconditional
+            // loads keep the staged values in registers)
+            stage_fetch<NE>(stv, win + (size_t)min(r + 1, nrhs - 1) * plane, piece);
             if (sactive) with_uniform<0, 4>(sg, [&](auto gc) __attribute__((always_inline)) {
                 cpx<T> out[2 * NG];
 #pragma unroll
@@ -643,6 +648,7 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
                 }
                 store_outputs(gc, out, r * plane);
             });
+            stage_put<NE>(stv, xin);
             lds_barrier();
         }
         return;
@@ -658,7 +664,7 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
             const XP xp = make_xp_sc(ph, box_node(ap1, level - 1, tb.z[ptp1]),
                                      box_node(ap2, level - 1, tb.z[tp2]), sp[bbl][0][ptp1], cp[bbl][0][ptp1],
                                      sp[bbl][1][tp2], cp[bbl][1][tp2]);
-            v[bbl][pc][ptp1 * Q + tp2] =
+            xin[(bbl * 4 + pc) * QQ + ptp1 * Q + tp2] =
                 cmulc(src[tp2], cis<T>(r0c[bbl][c1] * phase_dir(xp, ct0[bbl][c2], st0[bbl][c2])));
         }
     }
@@ -666,7 +672,7 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
     if (factive) {
         cpx<T> vv[Q];
 #pragma unroll
-        for (int tp2 = 0; tp2 < Q; ++tp2) vv[tp2] = v[fb][fac][fatp1 * Q + tp2];
+        for (int tp2 = 0; tp2 < Q; ++tp2) vv[tp2] = xin[(fb * 4 + fac) * QQ + fatp1 * Q + tp2];
         first_pass(vv);
     }
     lds_barrier();
