@@ -29,6 +29,12 @@ __device__ __forceinline__ void cfma(cpx<T> &acc, cpx<T> a, cpx<T> b) {
     acc.re = fma(a.re, b.re, fma(-a.im, b.im, acc.re));
     acc.im = fma(a.re, b.im, fma(a.im, b.re, acc.im));
 }
+// acc += a * conj(b)
+template <typename T>
+__device__ __forceinline__ void cfmac(cpx<T> &acc, cpx<T> a, cpx<T> b) {
+    acc.re = fma(a.re, b.re, fma(a.im, b.im, acc.re));
+    acc.im = fma(a.im, b.re, fma(-a.re, b.im, acc.im));
+}
 // acc += r * a  (r real)
 template <typename T>
 __device__ __forceinline__ void crfma(cpx<T> &acc, T r, cpx<T> a) {

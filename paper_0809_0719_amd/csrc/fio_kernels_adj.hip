@@ -592,7 +592,8 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
         for (int jj = 0; jj < 4; ++jj) {
             const double G = Gc[sb][jj][sc2 * Q + tp2];
 #pragma unroll
-            for (int o = 0; o < 2 * NG; ++o) E2[jj][o] = cis<T>(rc[sb][(o & 1) * Q + out_row(o)] * G);
+            for (int o = 0; o < 2 * NG; ++o)
+                if (sg + 4 * (o >> 1) < Q) E2[jj][o] = cis<T>(rc[sb][(o & 1) * Q + out_row(o)] * G);
         }
     }
     // inputs staged through LDS by coalesced loads, one right-hand side ahead:
@@ -633,12 +634,9 @@ __global__ __launch_bounds__(NT) void k_plevel_adj(Geom g, PhaseDev ph, Tables t
                 second_pass_j(gc, jj, z);
                 const double G = Gc[sb][jj][sc2 * Q + tp2];
 #pragma unroll
-                for (int o = 0; o < 2 * NG; ++o) {
-                    const cpx<T> add =
-                        cmulc(z[o], HOIST ? E2[jj][o] : cis<T>(rc[sb][(o & 1) * Q + out_row(o)] * G));
-                    acc[o].re += add.re;
-                    acc[o].im += add.im;
-                }
+                for (int o = 0; o < 2 * NG; ++o)
+                    if (gg + 4 * (o >> 1) < Q)
+                        cfmac(acc[o], z[o], HOIST ? E2[jj][o] : cis<T>(rc[sb][(o & 1) * Q + out_row(o)] * G));
             }
             cpx<T> *dst = dst0 + ri * plane;
 #pragma unroll

@@ -695,7 +695,8 @@ __global__ __launch_bounds__(NT) void k_xlevel(Geom g, PhaseDev ph, Tables tb, i
                 second_pass_c(gc, c, z);
                 const double rho = r0c[sb][c1];
 #pragma unroll
-                for (int o = 0; o < 2 * NG; ++o) cfma(out[o], cis<T>(rho * (c2 ? G1[o] : G0[o])), z[o]);
+                for (int o = 0; o < 2 * NG; ++o)
+                    if (decltype(gc)::value + 4 * (o >> 1) < Q) cfma(out[o], cis<T>(rho * (c2 ? G1[o] : G0[o])), z[o]);
             }
             store_outputs(gc, out, 0);
         });
