@@ -190,23 +190,40 @@ def bench_3d(N: int, q: int, steps: int, warmup: int, rows: int):
                       "config": {"workload": f"eq:ex3 3-D N={N} q={q}", "N": N, "q": q}}), flush=True)
 
 
-def bench_mixed(steps: int, warmup: int, nstreams: int):
+def bench_mixed(steps: int, warmup: int, nstreams: int, qmax: int = 16):
     """The uneven batch: 32 problems drawn by the mixed-batch recipe (N in
-    {128, 256, 512, 1024}, a tolerance in {1e-2, 1e-4, 1e-6} mapped to q =
-    5 / 7 / 9, eta ~ U[0, 0.3]^2), one right-hand side each, through a Batch
-    (internal streams) and, for comparison, one plan after another on one
-    stream.  value = problems per second through the batch."""
+    {128, 256, 512, 1024}, a tolerance in {1e-2, 1e-4, 1e-6}, eta ~
+    U[0, 0.3]^2), one right-hand side each.  q per (N, tolerance) class is
+    the library's own choice (fio_select_q: the smallest q in [3, qmax] whose
+    estimated eq:err on 64 sampled points is within the tolerance); a class
+    no such q reaches is reported as unreached and runs at the q with the
+    smallest estimate.  The batch runs through a Batch (internal streams)
+    and, for comparison, one plan after another on one stream.  value =
+    problems per second through the batch."""
     import torch
 
     import paper_0809_0719_amd as fio
     from workloads import mixed_batch, white_noise
 
     torch.cuda.set_device(0)
-    qmap = {1e-2: 5, 1e-4: 7, 1e-6: 9}
     probs = mixed_batch(6, n=32)
+    classes = {}
+    for p in probs:
+        key = (p["N"], p["tol"])
+        if key in classes:
+            continue
+        ph = fio.Phase(eta1=p["eta1"], eta2=p["eta2"])
+        q, err, tried = fio.select_q(p["N"], ph, tol=p["tol"], qmin=3, qmax=qmax, nrows=64, seed=7)
+        reached = err <= p["tol"]
+        if not reached:
+            q = min(tried, key=tried.get)
+            err = tried[q]
+        classes[key] = {"N": p["N"], "tol": p["tol"], "q": q, "est_err": err, "reached": bool(reached)}
+        print(f"class N={p['N']} tol={p['tol']:g}: q={q} est_err={err:.3g} reached={reached}", flush=True)
     plans, fs = [], []
     for p in probs:
-        plans.append(fio.Plan(p["N"], qmap[p["tol"]], fio.Phase(eta1=p["eta1"], eta2=p["eta2"])))
+        q = classes[(p["N"], p["tol"])]["q"]
+        plans.append(fio.Plan(p["N"], q, fio.Phase(eta1=p["eta1"], eta2=p["eta2"])))
         fs.append(torch.as_tensor(white_noise(p["N"], p["f_seed"] % 100000)).to(torch.complex64).cuda())
     batch = fio.Batch(plans, nstreams=nstreams)
     outs = [torch.empty_like(f) for f in fs]
@@ -225,13 +242,18 @@ def bench_mixed(steps: int, warmup: int, nstreams: int):
     t_serial = timed(lambda: [p.apply(f, out=o) for p, f, o in zip(plans, fs, outs)])
     counts = {}
     for p in probs:
-        key = f"N{p['N']}-q{qmap[p['tol']]}"
+        c = classes[(p["N"], p["tol"])]
+        key = f"N{p['N']}-q{c['q']}"
         counts[key] = counts.get(key, 0) + 1
+    unreached = [f"N{c['N']} tol {c['tol']:g} (best estimate {c['est_err']:.3g} at q={c['q']})"
+                 for c in classes.values() if not c["reached"]]
     print(json.dumps({"metric": "mixed-batch FIO applies/sec", "value": len(plans) / t_batch, "unit": "applies/s",
                       "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": t_batch * 1e3,
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
                       "data": "synthetic", "serial_ms_per_step": t_serial * 1e3,
                       "speedup_vs_serial": t_serial / t_batch,
+                      "q_selection": "fio_select_q per (N, tolerance) class, q in [3, %d]" % qmax,
+                      "classes": list(classes.values()), "unreached_classes": unreached,
                       "config": {"workload": "32 problems, eq:ex1 with eta ~ U[0,0.3]^2", "nstreams": nstreams,
                                  "problems": counts}}), flush=True)
 
@@ -319,11 +341,13 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=3072,
                     help="sampled points of the CPU baseline (about 10 s of the FP64 direct sum)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape (no autotuning)")
     ap.add_argument("--dims", type=int, choices=[2, 3], default=2,
                     help="3: the three-dimensional example eq:ex3 (forward applies, --N3, --q3)")
     ap.add_argument("--mixed", action="store_true",
                     help="the uneven batch of 32 problems through a Batch, against one plan after another")
     ap.add_argument("--nstreams", type=int, default=4)
+    ap.add_argument("--qmax", type=int, default=16, help="largest q --mixed may select")
     ap.add_argument("--N3", type=int, default=64)
     ap.add_argument("--q3", type=int, default=7)
     ap.add_argument("--feature", choices=["dphase", "amplitude"],
@@ -340,7 +364,7 @@ def main():
         copy_calibration()
         return
     if args.mixed:
-        bench_mixed(args.steps, args.warmup, args.nstreams)
+        bench_mixed(args.steps, args.warmup, args.nstreams, args.qmax)
         return
     if args.dims == 3:
         bench_3d(args.N3, args.q3, args.steps, args.warmup, 64 if args.N3 <= 128 else 16)
@@ -357,6 +381,9 @@ def main():
     torch.cuda.set_device(0)
     N, q, R = args.N, args.q, args.nrhs
     plan = fio.Plan(N, q, fio.Phase(), dtype=torch.complex64, nrhs_max=R, contract=args.contract)
+    # launch shape measured on this device before the timed region (the
+    # shapes all give the same results)
+    tune = plan.autotune(R) if not args.no_tune else {"candidates": 0, **plan.shape()}
     f_host = white_noise(N, 3, nrhs=R)
     f = torch.as_tensor(f_host).to(torch.complex64).cuda()
     u = torch.empty_like(f)
@@ -463,6 +490,7 @@ def main():
                                f"complex white-noise f, forward+adjoint per step",
                    "N": N, "q": q, "nrhs": R, "s": plan.s, "lm": plan.lm, "phase_dtype": "f64",
                    "weight_dtype": "f32", "contract": args.contract},
+        "launch_shape": tune,
         "plain_forward_applies_per_s": plain,
         "rel_err_vs_direct_sum": errs,
         "meets_metric_tolerance": meets,

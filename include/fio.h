@@ -128,7 +128,10 @@ typedef struct {
     int64_t weights_per_level;/* complex weights per level per RHS = N^2 q^2      */
     int64_t workspace_bytes;  /* device memory owned by the plan                  */
     int max_box_sources;      /* largest number of sources in a level-(L-s) box */
-    int nrhs_max;             /* right-hand sides per chunk                        */
+    int nrhs_max;             /* right-hand sides the weight buffers hold          */
+    int chunk;                /* right-hand sides per pass (nrhs_max unless tuned) */
+    int switch_items;         /* pair items per workgroup of the matrix-core
+                                 switches (16 unless tuned)                        */
 } fio_plan_info_t;
 
 /* Create a plan for an N x N problem with q Chebyshev points per dimension
@@ -153,13 +156,46 @@ int fio_set_phase(fio_plan_t plan, const fio_phase_t *phase);
 
 int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info);
 
+/* Launch-shape autotuner (end of Sec. 4: the vectorised butterfly; the
+ * shapes are this library's own).  Times a forward and an adjoint apply of
+ * nrhs right-hand sides on the plan's device for each candidate pair
+ *   switch_items in {8, 16, 32}   (pair items per workgroup of the
+ *                                  matrix-core switches),
+ *   chunk in {32, 64, ..., nrhs_max} (right-hand sides per pass),
+ * and keeps the fastest in the plan for every later apply.  Every candidate
+ * runs the same arithmetic on each right-hand side (the kernels each chunk
+ * takes do not change while chunk >= 32), so results do not depend on the
+ * choice; a chunk shape is a candidate only when it leaves each right-hand
+ * side of a call of nrhs in a pass of >= 32 (or in the same last pass) as
+ * the current shape does.  Plans where nothing applies (complex128, q > 9,
+ * nrhs_max, nrhs or the current chunk below 32) keep their shape and report
+ * it with candidates = 0.
+ *   nrhs: right-hand sides per call to tune for (inputs are zero-filled
+ *         device buffers the call allocates and frees: 2 nrhs N^2 complex).
+ *   out:  host pointer or NULL; receives the choice and the measured times
+ *         (milliseconds per forward + adjoint pair; best and default shape).
+ * Synchronises the device.  FIO_EINVAL on bad arguments, FIO_ENOMEM,
+ * FIO_EDEVICE. */
+typedef struct {
+    int chunk, switch_items;   /* the shape kept                          */
+    int candidates;            /* shapes timed (0: nothing to tune)       */
+    double best_ms;            /* forward + adjoint at the kept shape     */
+    double default_ms;         /* forward + adjoint at the default shape  */
+} fio_tune_t;
+int fio_plan_autotune(fio_plan_t plan, int nrhs, fio_tune_t *out);
+/* Set the launch shape directly: chunk in [1, nrhs_max], switch_items in
+ * {8, 16, 32} (the shapes fio_plan_autotune chooses among).  FIO_EINVAL
+ * otherwise. */
+int fio_plan_set_shape(fio_plan_t plan, int chunk, int switch_items);
+
 /* Forward butterfly u = B f (approximates eq:dfio).
  *   f: device, nrhs x N x N complex (plan dtype), f[r][k1+N/2][k2+N/2].
  *      Read only.
  *   u: device, nrhs x N x N complex (plan dtype), u[r][i1][i2] = u_r(i1/N,
  *      i2/N).  Fully overwritten.  The byte ranges of f and u (nrhs N^2
  *      complex values each) must not share a byte.
- *   nrhs >= 1 right-hand sides, processed in chunks of the plan's nrhs_max;
+ *   nrhs >= 1 right-hand sides, processed in chunks of the plan's chunk
+ *   (nrhs_max unless fio_plan_autotune chose fewer);
  *   within a chunk the kernel values of the levels and the switch are
  *   computed once and applied to every right-hand side.
  *   dtype: FIO_C64 or FIO_C128, the element type of f and u as the caller

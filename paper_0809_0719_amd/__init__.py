@@ -45,7 +45,7 @@ _LIB_PATH = os.path.join(_HERE, "libfio.so")
 
 # every symbol include/fio.h declares
 EXPORTED_SYMBOLS = (
-    "fio_plan", "fio_plan_ex", "fio_set_phase", "fio_plan_get_info", "fio_apply",
+    "fio_plan", "fio_plan_ex", "fio_set_phase", "fio_plan_get_info", "fio_plan_autotune", "fio_plan_set_shape", "fio_apply",
     "fio_apply_adjoint", "fio_debug_stage", "fio_destroy", "fio_last_error",
     "fio_profile_enable", "fio_profile_read", "fio_apply_dphase", "fio_apply_amplitude",
     "fio_apply_amplitude_adjoint", "fio_apply_amplitude_noalloc", "fio_batch_create", "fio_batch_apply", "fio_batch_apply_adjoint",
@@ -89,7 +89,13 @@ class _CInfo(ctypes.Structure):
                 ("lm", ctypes.c_int), ("dtype", ctypes.c_int), ("contract", ctypes.c_int),
                 ("n_pairs", ctypes.c_int64),
                 ("weights_per_level", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
-                ("max_box_sources", ctypes.c_int), ("nrhs_max", ctypes.c_int)]
+                ("max_box_sources", ctypes.c_int), ("nrhs_max", ctypes.c_int), ("chunk", ctypes.c_int),
+                ("switch_items", ctypes.c_int)]
+
+
+class _CTune(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int), ("switch_items", ctypes.c_int), ("candidates", ctypes.c_int),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -109,6 +115,8 @@ def load_library():
     lib.fio_plan_ex.argtypes = [i, i, ctypes.POINTER(_CPhase), ctypes.POINTER(_COpts), ctypes.POINTER(vp)]
     lib.fio_set_phase.argtypes = [vp, ctypes.POINTER(_CPhase)]
     lib.fio_plan_get_info.argtypes = [vp, ctypes.POINTER(_CInfo)]
+    lib.fio_plan_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(_CTune)]
+    lib.fio_plan_set_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.fio_apply.argtypes = [vp, vp, vp, i, i, vp]
     lib.fio_apply_adjoint.argtypes = [vp, vp, vp, i, i, vp]
     lib.fio_apply_dphase.argtypes = [vp, vp, vp, vp, vp, i, vp]
@@ -208,6 +216,25 @@ class Plan:
     def set_phase(self, phase: Phase):
         _check(load_library().fio_set_phase(self._h, ctypes.byref(_cphase(phase))), "fio_set_phase")
         self.phase = phase
+
+    def shape(self) -> dict:
+        """The launch shape applies use: right-hand sides per pass and pair
+        items per workgroup of the matrix-core switches."""
+        info = _CInfo()
+        _check(load_library().fio_plan_get_info(self._h, ctypes.byref(info)), "fio_plan_get_info")
+        return {"chunk": int(info.chunk), "switch_items": int(info.switch_items)}
+
+    def set_shape(self, chunk: int, switch_items: int):
+        """Set the launch shape directly (``fio_plan_set_shape``)."""
+        _check(load_library().fio_plan_set_shape(self._h, int(chunk), int(switch_items)), "fio_plan_set_shape")
+
+    def autotune(self, nrhs: int) -> dict:
+        """Time the launch shapes for calls of nrhs right-hand sides and keep
+        the fastest (``fio_plan_autotune``; synchronises the device)."""
+        t = _CTune()
+        _check(load_library().fio_plan_autotune(self._h, int(nrhs), ctypes.byref(t)), "fio_plan_autotune")
+        return {"chunk": int(t.chunk), "switch_items": int(t.switch_items), "candidates": int(t.candidates),
+                "best_ms": float(t.best_ms), "default_ms": float(t.default_ms)}
 
     # -- helpers ------------------------------------------------------------
     def _prep(self, x: torch.Tensor, name: str):

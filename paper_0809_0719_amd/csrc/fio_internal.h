@@ -29,6 +29,7 @@ struct Geom {
     int s;       // levels skipped at each end
     int lm;      // switch level
     double rho_scale;  // (sqrt(2)/2) N : |k| = rho_scale * p1 (eq:polar)
+    int sw_ppw;        // items per workgroup of the matrix-core switches (8, 16 or 32; tuned)
 };
 
 // Device-resident tables of a plan (all FP64 except where a float copy is kept).
@@ -106,6 +107,7 @@ hipError_t launch_init_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables 
 // planes `plane` apart; the same operators as the vector kernels of
 // launch_switch and launch_switch_adj.
 bool switch_mfma_supported(int q, int nrhs);
+bool switch_ppw_supported(int ppw);
 hipError_t launch_switch_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs, size_t plane,
                               hipStream_t st);
 bool switch_adj_mfma_supported(int q, int nrhs);

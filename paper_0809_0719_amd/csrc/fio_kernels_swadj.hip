@@ -40,7 +40,6 @@ namespace {
 using f32x4 = __attribute__((ext_vector_type(4))) float;
 
 constexpr int SA_RC = 64;   // right-hand sides per item (16 per wave)
-constexpr int SA_PPW = 16;  // items per workgroup
 
 template <int Q>
 constexpr int sa_srow() { return (Q * Q) | 1; }  // odd row stride (complex) of the staging buffer
@@ -62,7 +61,7 @@ constexpr int SH_RC = SA_RC / 2;  // right-hand sides per half item
 template <int Q>
 constexpr int sh_lpt() { return (SH_RC * Q * Q + NT - 1) / NT; }
 
-template <int Q>
+template <int Q, int PPW>
 __global__ __launch_bounds__(NT, 3) void k_switch_adj_mm(Geom g, PhaseDev ph, Tables tb, cpx<float> *__restrict__ w,
                                                          int nrhs, size_t plane, size_t nitems, int nchunk) {
     constexpr int QQ = Q * Q, H = Q / 2;
@@ -76,11 +75,11 @@ __global__ __launch_bounds__(NT, 3) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
     const int lo = lane & 15, hi = lane >> 4;
     const int lA = g.lm, lB = g.L - g.lm;
     const size_t nBl = (size_t)1 << (2 * lB);
-    // half items h = 2 item + half; a workgroup takes 2 SA_PPW of them in turn
+    // half items h = 2 item + half; a workgroup takes 2 PPW of them in turn
     const size_t nhalf = 2 * nitems;
-    const size_t h0 = linear_block() * (2 * SA_PPW);
+    const size_t h0 = linear_block() * (2 * PPW);
     if (h0 >= nhalf) return;  // whole workgroup
-    const int nh = (int)min((size_t)(2 * SA_PPW), nhalf - h0);
+    const int nh = (int)min((size_t)(2 * PPW), nhalf - h0);
     const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
     double hz[H > 0 ? H : 1];
 #pragma unroll
@@ -262,7 +261,7 @@ __global__ __launch_bounds__(NT, 3) void k_switch_adj_mm(Geom g, PhaseDev ph, Ta
 // the outputs go back through the same buffer once every node is done.
 bool switch_mfma_supported(int q, int nrhs) { return q >= QMIN && q <= 9 && nrhs >= 32; }
 
-template <int Q>
+template <int Q, int PPW>
 __global__ __launch_bounds__(NT, 2) void k_switch_mm(Geom g, PhaseDev ph, Tables tb, cpx<float> *__restrict__ w,
                                                      int nrhs, size_t plane, size_t nitems, int nchunk) {
     constexpr int QQ = Q * Q, H = Q / 2;
@@ -279,9 +278,9 @@ __global__ __launch_bounds__(NT, 2) void k_switch_mm(Geom g, PhaseDev ph, Tables
     const int lo = lane & 15, hi = lane >> 4;
     const int lA = g.lm, lB = g.L - g.lm;
     const size_t nBl = (size_t)1 << (2 * lB);
-    const size_t item0 = linear_block() * SA_PPW;
+    const size_t item0 = linear_block() * PPW;
     if (item0 >= nitems) return;  // whole workgroup
-    const int nit = (int)min((size_t)SA_PPW, nitems - item0);
+    const int nit = (int)min((size_t)PPW, nitems - item0);
     const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
     double hz[H > 0 ? H : 1];
 #pragma unroll
@@ -468,16 +467,24 @@ __global__ __launch_bounds__(NT, 2) void k_switch_mm(Geom g, PhaseDev ph, Tables
     }
 }
 
+bool switch_ppw_supported(int ppw) { return ppw == 8 || ppw == 16 || ppw == 32; }
+
 hipError_t launch_switch_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs,
                               size_t plane, hipStream_t st) {
-    if (!switch_mfma_supported(g.q, nrhs)) return hipErrorInvalidValue;
+    if (!switch_mfma_supported(g.q, nrhs) || !switch_ppw_supported(g.sw_ppw)) return hipErrorInvalidValue;
     const size_t npairs = (size_t)1 << (2 * g.L);
     const int nchunk = (nrhs + SA_RC - 1) / SA_RC;
     const size_t nitems = npairs * (size_t)nchunk;
-    const size_t nblk = (nitems + SA_PPW - 1) / SA_PPW;
-#define L_SFM(Q)                                                                                           \
-    hipLaunchKernelGGL((k_switch_mm<Q>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, (cpx<float> *)w, nrhs, \
+    const size_t nblk = (nitems + g.sw_ppw - 1) / g.sw_ppw;
+#define L_SFP(Q, P)                                                                                           \
+    hipLaunchKernelGGL((k_switch_mm<Q, P>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, (cpx<float> *)w, nrhs, \
                        plane, nitems, nchunk);
+#define L_SFM(Q)                                   \
+    {                                              \
+        if (g.sw_ppw == 8) L_SFP(Q, 8)             \
+        else if (g.sw_ppw == 16) L_SFP(Q, 16)      \
+        else L_SFP(Q, 32)                          \
+    }
     switch (g.q) {
         case 3: L_SFM(3) break;
         case 4: L_SFM(4) break;
@@ -489,19 +496,26 @@ hipError_t launch_switch_mfma(const Geom &g, const PhaseDev &ph, const Tables &t
         default: return hipErrorInvalidValue;
     }
 #undef L_SFM
+#undef L_SFP
     return hipGetLastError();
 }
 
 hipError_t launch_switch_adj_mfma(const Geom &g, const PhaseDev &ph, const Tables &tb, void *w, int nrhs,
                                   size_t plane, hipStream_t st) {
-    if (!switch_adj_mfma_supported(g.q, nrhs)) return hipErrorInvalidValue;
+    if (!switch_adj_mfma_supported(g.q, nrhs) || !switch_ppw_supported(g.sw_ppw)) return hipErrorInvalidValue;
     const size_t npairs = (size_t)1 << (2 * g.L);
     const int nchunk = (nrhs + SA_RC - 1) / SA_RC;
     const size_t nitems = npairs * (size_t)nchunk;
-    const size_t nblk = (nitems + SA_PPW - 1) / SA_PPW;
-#define L_SAM(Q)                                                                                          \
-    hipLaunchKernelGGL((k_switch_adj_mm<Q>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, (cpx<float> *)w, nrhs, \
+    const size_t nblk = (nitems + g.sw_ppw - 1) / g.sw_ppw;
+#define L_SAP(Q, P)                                                                                               \
+    hipLaunchKernelGGL((k_switch_adj_mm<Q, P>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, (cpx<float> *)w, nrhs, \
                        plane, nitems, nchunk);
+#define L_SAM(Q)                                   \
+    {                                              \
+        if (g.sw_ppw == 8) L_SAP(Q, 8)             \
+        else if (g.sw_ppw == 16) L_SAP(Q, 16)      \
+        else L_SAP(Q, 32)                          \
+    }
     switch (g.q) {
         case 3: L_SAM(3) break;
         case 4: L_SAM(4) break;
@@ -513,6 +527,7 @@ hipError_t launch_switch_adj_mfma(const Geom &g, const PhaseDev &ph, const Table
         default: return hipErrorInvalidValue;
     }
 #undef L_SAM
+#undef L_SAP
     return hipGetLastError();
 }
 

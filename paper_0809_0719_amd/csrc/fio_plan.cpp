@@ -87,6 +87,7 @@ double lagrange(const std::vector<double> &z, int t, double u) {
 
 struct fio_plan_s {
     int N = 0, q = 0, L = 0, s = 0, lm = 0, dtype = FIO_C64, device = 0, nrhs_max = 1;
+    int chunk = 1;  // right-hand sides per pass (<= nrhs_max; tuned)
     int contract = FIO_CONTRACT_FP;
     fio_phase_t phase{};
     int max_box = 0;
@@ -287,6 +288,7 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     p->lm = lm;
     p->dtype = dtype;
     p->nrhs_max = nrhs_max;
+    p->chunk = nrhs_max;
     p->contract = contract;
     p->phase = *phase;
     hipError_t e = hipGetDevice(&p->device);
@@ -420,6 +422,7 @@ int fio_plan_ex(int N, int q, const fio_phase_t *phase, const fio_plan_opts_t *o
     p->geom.s = s;
     p->geom.lm = lm;
     p->geom.rho_scale = std::sqrt(2.0) / 2.0 * N;
+    p->geom.sw_ppw = 16;
 
     // tables of the initialisation on the matrix cores
     p->init_mm = dtype == FIO_C64 && init_mfma_supported(q, s);
@@ -452,6 +455,112 @@ int fio_set_phase(fio_plan_t plan, const fio_phase_t *phase) {
     return FIO_OK;
 }
 
+int fio_plan_autotune(fio_plan_t plan, int nrhs, fio_tune_t *out) {
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (nrhs < 1) return fail(FIO_EINVAL, "nrhs must be >= 1 (got %d)", nrhs);
+    if ((rc = set_device(plan))) return rc;
+    fio_tune_t res{};
+    res.chunk = plan->chunk;
+    res.switch_items = plan->geom.sw_ppw;
+    // candidates: chunks of >= 32 right-hand sides (the same kernels for every
+    // chunk), items per workgroup of the matrix-core switches
+    // A chunk shape c is a candidate when it gives every right-hand side of a
+    // call of nrhs the kernels the plan's current shape gives it: chunks of
+    // >= 32 take the same kernels, so both shapes must leave no remainder
+    // below 32, or the same one.
+    auto same_kernels = [&](int c) {
+        const int tc = nrhs % c, td = nrhs % plan->chunk;
+        return tc == td || ((tc == 0 || tc >= 32) && (td == 0 || td >= 32));
+    };
+    std::vector<int> chunks;
+    const int cmax = std::min(plan->nrhs_max, nrhs);
+    if (plan->dtype == FIO_C64 && plan->q <= 9 && plan->chunk >= 32) {
+        for (int c = 32; c <= cmax; c *= 2)
+            if (same_kernels(c)) chunks.push_back(c);
+        if (cmax >= 32 && (chunks.empty() || chunks.back() != cmax) && same_kernels(cmax)) chunks.push_back(cmax);
+    }
+    if (chunks.empty()) {
+        if (out) *out = res;
+        return FIO_OK;
+    }
+    const size_t bytes = (size_t)nrhs * plan->N * plan->N * 8;
+    void *f = nullptr, *u = nullptr;
+    hipError_t e = hipMalloc(&f, bytes);
+    if (e == hipSuccess) e = hipMalloc(&u, bytes);
+    if (e == hipSuccess) e = hipMemset(f, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(u, 0, bytes);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    const int keep_chunk = plan->chunk, keep_ppw = plan->geom.sw_ppw;
+    double best = 1e300, dflt = 0.0;
+    int best_chunk = keep_chunk, best_ppw = keep_ppw, ncand = 0;
+    auto timed = [&](double *ms) -> int {
+        int r2 = FIO_OK;
+        for (int rep = 0; rep < 3 && !r2; ++rep) {  // one warm-up, then the faster of two
+            hipError_t e2 = hipEventRecord(t0, nullptr);
+            if (e2 != hipSuccess) return hip_fail(e2, "autotune event");
+            if ((r2 = fio_apply(plan, f, u, nrhs, FIO_C64, nullptr))) break;
+            if ((r2 = fio_apply_adjoint(plan, u, f, nrhs, FIO_C64, nullptr))) break;
+            if ((e2 = hipEventRecord(t1, nullptr)) != hipSuccess || (e2 = hipEventSynchronize(t1)) != hipSuccess)
+                return hip_fail(e2, "autotune event");
+            float m = 0.f;
+            if ((e2 = hipEventElapsedTime(&m, t0, t1)) != hipSuccess) return hip_fail(e2, "autotune event");
+            if (rep > 0 && m < *ms) *ms = m;
+        }
+        return r2;
+    };
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "autotune buffers");
+    } else {
+        for (int c : chunks) {
+            for (int ppw : {8, 16, 32}) {
+                plan->chunk = c;
+                plan->geom.sw_ppw = ppw;
+                double ms = 1e300;
+                if ((rc = timed(&ms))) break;
+                ++ncand;
+                if (c == keep_chunk && ppw == keep_ppw) dflt = ms;
+                if (ms < best) {
+                    best = ms;
+                    best_chunk = c;
+                    best_ppw = ppw;
+                }
+            }
+            if (rc) break;
+        }
+    }
+    plan->chunk = rc ? keep_chunk : best_chunk;
+    plan->geom.sw_ppw = rc ? keep_ppw : best_ppw;
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipFree(f);
+    (void)hipFree(u);
+    if (rc) return rc;
+    res.chunk = plan->chunk;
+    res.switch_items = plan->geom.sw_ppw;
+    res.candidates = ncand;
+    res.best_ms = best;
+    res.default_ms = dflt;
+    if (out) *out = res;
+    return FIO_OK;
+}
+
+int fio_plan_set_shape(fio_plan_t plan, int chunk, int switch_items) {
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (chunk < 1 || chunk > plan->nrhs_max)
+        return fail(FIO_EINVAL, "chunk must be in [1, %d] (got %d)", plan->nrhs_max, chunk);
+    if (!switch_ppw_supported(switch_items))
+        return fail(FIO_EINVAL, "switch_items must be 8, 16 or 32 (got %d)", switch_items);
+    plan->chunk = chunk;
+    plan->geom.sw_ppw = switch_items;
+    return FIO_OK;
+}
+
 int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info) {
     int rc = check_plan(plan);
     if (rc) return rc;
@@ -468,6 +577,8 @@ int fio_plan_get_info(fio_plan_t plan, fio_plan_info_t *info) {
     info->workspace_bytes = (int64_t)plan->total_bytes;
     info->nrhs_max = plan->nrhs_max;
     info->max_box_sources = plan->max_box;
+    info->chunk = plan->chunk;
+    info->switch_items = plan->geom.sw_ppw;
     return FIO_OK;
 }
 
@@ -790,8 +901,8 @@ int fio_apply(fio_plan_t plan, const void *f, void *u, int nrhs, int dtype, void
     if ((rc = set_device(plan))) return rc;
     const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
     hipStream_t st = (hipStream_t)stream;
-    for (int r = 0; r < nrhs; r += plan->nrhs_max) {
-        const int nr = std::min(plan->nrhs_max, nrhs - r);
+    for (int r = 0; r < nrhs; r += plan->chunk) {
+        const int nr = std::min(plan->chunk, nrhs - r);
         rc = run_forward(plan, (const char *)f + r * step, (char *)u + r * step, nr, -1, nullptr, st);
         if (rc) return rc;
     }
@@ -805,8 +916,8 @@ int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, int dty
     if ((rc = set_device(plan))) return rc;
     const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
     hipStream_t st = (hipStream_t)stream;
-    for (int r = 0; r < nrhs; r += plan->nrhs_max) {
-        const int nr = std::min(plan->nrhs_max, nrhs - r);
+    for (int r = 0; r < nrhs; r += plan->chunk) {
+        const int nr = std::min(plan->chunk, nrhs - r);
         rc = run_adjoint(plan, (const char *)u + r * step, (char *)f + r * step, nr, st);
         if (rc) return rc;
     }
