@@ -258,13 +258,15 @@ def bench_mixed(steps: int, warmup: int, nstreams: int, qmax: int = 16):
                                  "problems": counts}}), flush=True)
 
 
-def bench_feature(kind: str, N: int, q: int, rank: int, steps: int, warmup: int):
+def bench_feature(kind: str, N: int, q: int, rank: int, nrhs: int, steps: int, warmup: int):
     """One of the extensions at the benchmark's (N, q), timed beside the plain
     butterfly on the same plan:
     * dphase: u and its derivatives du/da1, du/da2 with respect to the ellipse
-      scalings of one right-hand side (fio_apply_dphase, which takes the
-      right-hand sides one at a time); value = such triples per second,
-      against the plain single-right-hand-side forward;
+      scalings of `nrhs` right-hand sides at once (fio_apply_dphase on a plan
+      of nrhs_max = nrhs, which takes them in even chunks of at most nrhs/3
+      whose level kernels share their kernel values); value = such triples
+      per second, against the plain batched forward of the same right-hand
+      sides; the single-right-hand-side cost is reported beside it;
     * amplitude: a separated amplitude a(x,k) = sum_t g_t(x) h_t(k) of the
       given rank, forward and adjoint (fio_apply_amplitude[_adjoint]); value
       = amplitude applies per second (a forward and an adjoint count two),
@@ -287,14 +289,19 @@ def bench_feature(kind: str, N: int, q: int, rank: int, steps: int, warmup: int)
         return (time.perf_counter() - t0) / steps
 
     c64 = torch.complex64
+    extra = {}
     if kind == "dphase":
-        plan = fio.Plan(N, q, fio.Phase(), dtype=c64)
-        f = torch.as_tensor(white_noise(N, 3)).to(c64).cuda()
-        u = torch.empty_like(f)
-        t_feat = timed(lambda: plan.apply_dphase(f))
-        t_plain = timed(lambda: plan.apply(f, out=u))
-        value = 1 / t_feat
-        metric, cfg = "FIO + phase-derivative applies/sec", {"nrhs": 1}
+        plan = fio.Plan(N, q, fio.Phase(), dtype=c64, nrhs_max=nrhs)
+        fr = torch.as_tensor(white_noise(N, 3, nrhs=nrhs)).to(c64).cuda()
+        ur = torch.empty_like(fr)
+        t_feat = timed(lambda: plan.apply_dphase(fr))
+        t_plain = timed(lambda: plan.apply(fr, out=ur))
+        t_one = timed(lambda: plan.apply_dphase(fr[0]))
+        t_one_plain = timed(lambda: plan.apply(fr[0], out=ur[0]))
+        value = nrhs / t_feat
+        metric, cfg = "FIO + phase-derivative applies/sec", {"nrhs": nrhs}
+        extra = {"single_rhs": {"ms": t_one * 1e3, "plain_ms": t_one_plain * 1e3,
+                                "cost_vs_plain": t_one / t_one_plain}}
     else:
         plan = fio.Plan(N, q, fio.Phase(), dtype=c64, nrhs_max=rank)
         g_h, h_h = amplitude_factors(N, rank, 7)
@@ -321,7 +328,7 @@ def bench_feature(kind: str, N: int, q: int, rank: int, steps: int, warmup: int)
     print(json.dumps({"metric": metric, "value": value, "unit": "applies/s", "n_gpus": 1, "steps": steps,
                       "warmup": warmup, "ms_per_step": t_feat * 1e3, "higher_is_better": True, "scaling": "weak",
                       "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-                      "plain_ms_per_step": t_plain * 1e3, "cost_vs_plain": t_feat / t_plain,
+                      "plain_ms_per_step": t_plain * 1e3, "cost_vs_plain": t_feat / t_plain, **extra,
                       "config": dict({"workload": f"eq:ex1 FIO butterfly N={N} q={q}, {kind}"}, **cfg)}),
           flush=True)
 
@@ -370,7 +377,7 @@ def main():
         bench_3d(args.N3, args.q3, args.steps, args.warmup, 64 if args.N3 <= 128 else 16)
         return
     if args.feature:
-        bench_feature(args.feature, args.N, args.q, args.rank, args.steps, args.warmup)
+        bench_feature(args.feature, args.N, args.q, args.rank, args.nrhs, args.steps, args.warmup)
         return
 
     import torch

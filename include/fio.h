@@ -230,11 +230,15 @@ int fio_apply_adjoint(fio_plan_t plan, const void *u, void *f, int nrhs, int dty
  *   u: device, nrhs x N x N, or NULL (then the primal output is not stored).
  *   du_da1, du_da2: device, nrhs x N x N each; fully overwritten.
  *   The outputs must not overlap f or each other.  Requires q <= 12.
- * Workspace: three N^2 q^2 planes in each of two buffers -- the plan's own
- * weight buffers when nrhs_max >= 3, else two buffers the first call
- * allocates and the plan keeps until fio_destroy (FIO_ENOMEM if that fails).
- * The right-hand sides are processed one after another.  Asynchronous on
- * `stream`; FIO_EINVAL before any launch on bad arguments. */
+ * Workspace: three N^2 q^2 planes per right-hand side in each of two
+ * buffers -- the plan's own weight buffers when nrhs_max >= 3, else two
+ * buffers of three planes that the first call allocates and the plan keeps
+ * until fio_destroy (FIO_ENOMEM if that fails).  The right-hand sides go in
+ * chunks of at most nrhs_max / 3 (at least one), split as evenly as they
+ * come; the level kernels of a chunk share their kernel values and
+ * derivative factors, so a chunk's results equal those of one right-hand
+ * side at a time bit for bit.  Asynchronous on `stream`; FIO_EINVAL before
+ * any launch on bad arguments. */
 int fio_apply_dphase(fio_plan_t plan, const void *f, void *u, void *du_da1, void *du_da2, int nrhs,
                      void *stream);
 

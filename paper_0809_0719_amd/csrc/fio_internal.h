@@ -151,14 +151,16 @@ hipError_t launch_init_adj(int dtype, const Geom &g, const PhaseDev &ph, const T
                            const Sources &src, const void *w_in, void *f, hipStream_t st);
 
 // Forward pass with the derivatives with respect to the phase's velocity
-// scalings (fio_kernels_tan.hip), one right-hand side: weights are three
-// planes `plane` complex values apart (primal, d/da1, d/da2).  `step`:
+// scalings (fio_kernels_tan.hip): the weights of one right-hand side are
+// three planes `plane` complex values apart (primal, d/da1, d/da2).  `step`:
 // 0 initialisation (in = f), 1 p-level, 2 switch (in place on out),
 // 3 x-level, 4 termination (out = u or NULL, u1 = du/da1, u2 = du/da2).
+// The level steps (1, 3) take `nrhs` right-hand sides whose planes start
+// 3 * plane apart; the others take one and ignore `nrhs`.
 bool tangent_supported_q(int q);
 hipError_t launch_tangent_step(int dtype, int step, const Geom &g, const PhaseDev &ph, const Tables &tb,
                                const Sources &src, int level, const void *in, void *out, size_t plane,
-                               void *u1, void *u2, hipStream_t st);
+                               void *u1, void *u2, int nrhs, hipStream_t st);
 
 // Direct sum of eq:dfio at listed targets (FP64 phase, exponentials and sums)
 // and the SplitMix64 unit-modulus probe (fio_kernels_direct.hip).

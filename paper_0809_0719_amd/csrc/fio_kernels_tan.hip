@@ -157,23 +157,44 @@ __global__ __launch_bounds__(NT) void k_init_tan(Geom g, PhaseDev ph, Tables tb,
     }
 }
 
+// A thread's elements tid + n NT (n < ceil(NE / NT)) of three planes `plane`
+// values apart: every load is issued (indices past NE clamped to NE - 1, so
+// no element is conditional), their waits fall where the values are used.
+template <typename T, int NE, int NP = (NE + NT - 1) / NT>
+__device__ __forceinline__ void fetch_planes(cpx<T> (&d)[3][NP], const cpx<T> *src, size_t plane, int tid) {
+#pragma unroll
+    for (int n = 0; n < NP; ++n) {
+        const int i = min(tid + n * NT, NE - 1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k][n] = src[k * plane + i];
+    }
+}
+
 // ===========================================================================
 // p-recursion (eq:alg2b) with derivatives, one workgroup per block (A_p, B),
 // the four outputs one after another:
 //   v   = Ep . in,       d v = Ep . (d in + 2 pi i dPhi_p . in)
 //   out = conj Er . K v, d out = conj Er . K d v - 2 pi i dPhi_r . out
+// The kernel values of the four outputs (Ep, Er and the factors
+// 2 pi dPhi of the derivative terms) are made once per block in LDS and
+// serve nrhs right-hand sides, whose three planes start rstride values apart.
 // ===========================================================================
 template <typename T, int Q>
 __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables tb, int level,
                                                    const cpx<T> *__restrict__ win,
-                                                   cpx<T> *__restrict__ wout, size_t plane) {
+                                                   cpx<T> *__restrict__ wout, size_t plane, int nrhs,
+                                                   size_t rstride) {
     constexpr int QQ = Q * Q;
+    constexpr double TWO_PI = 6.283185307179586476925286766559;
     __shared__ cpx<T> v[3][4 * QQ];
     __shared__ cpx<T> W[3][2 * QQ];
-    __shared__ T Ms[2 * QQ];
     __shared__ double rc[2 * Q], ctc[2 * Q], stc[2 * Q];
     __shared__ double rb[Q], ctb[Q], stb[Q];
     __shared__ G3 Gc[2 * Q], Gb[Q];
+    __shared__ cpx<T> Ep[4][4 * QQ];  // E(x0(A_j), p^{B_c}_t')
+    __shared__ T Sp[2][4][4 * QQ];    // 2 pi rho dPhi_k(x0(A_j), .) at p^{B_c}_t'
+    __shared__ cpx<T> Er[4][QQ];      // E(x0(A_j), p^B_t)
+    __shared__ T Sr[2][4][QQ];
 
     const int tid = threadIdx.x;
     const int lB = g.L - level;
@@ -185,8 +206,6 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
     morton_decode(mB, b1, b2);
     morton_decode(mAp, ap1, ap2);
 
-    const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) Ms[i] = Mg[i];
     if (tid < 2 * Q) {
         const int c = tid / Q, t = tid - c * Q;
         const double z = tb.z[t];
@@ -205,7 +224,7 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
         stb[t] = s_;
     }
     __syncthreads();
-    const cpx<T> *src = win + blk * (4 * QQ);
+    // kernel values of output j into table slot sl
     for (int j = 0; j < 4; ++j) {
         const int a1 = 2 * ap1 + (j >> 1), a2 = 2 * ap2 + (j & 1);
         const XP xp = make_xp(ph, box_centre(a1, level), box_centre(a2, level));
@@ -218,51 +237,113 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
             const int tp1 = t / Q, tp2 = t - tp1 * Q;
             const double rho = rc[c1 * Q + tp1];
             const G3 gg = Gc[c2 * Q + tp2];
-            const cpx<T> e = cis<T>(rho * gg.g);
-            const cpx<T> in0 = src[i];
-            v[0][i] = cmul(e, in0);
-            v[1][i] = cmul(e, cadd(src[plane + i], i2pi(rho * gg.d1, in0)));
-            v[2][i] = cmul(e, cadd(src[2 * plane + i], i2pi(rho * gg.d2, in0)));
+            Ep[j][i] = cis<T>(rho * gg.g);
+            Sp[0][j][i] = (T)(TWO_PI * (rho * gg.d1));
+            Sp[1][j][i] = (T)(TWO_PI * (rho * gg.d2));
         }
-        __syncthreads();
-        for (int i = tid; i < 3 * 2 * QQ; i += NT) {
-            const int k = i / (2 * QQ), ii = i - k * 2 * QQ;
-            const int c1 = ii / QQ, rr = ii - c1 * QQ;
-            const int tp1 = rr / Q, t2 = rr - tp1 * Q;
-            cpx<T> acc = {(T)0, (T)0};
-#pragma unroll
-            for (int c2 = 0; c2 < 2; ++c2) {
-                const cpx<T> *vv = v[k] + (2 * c1 + c2) * QQ + tp1 * Q;
-                const T *m = Ms + c2 * QQ + t2 * Q;
-#pragma unroll
-                for (int tp2 = 0; tp2 < Q; ++tp2) crfma(acc, m[tp2], vv[tp2]);
-            }
-            W[k][ii] = acc;
-        }
-        __syncthreads();
-        cpx<T> *dst = wout + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
         for (int i = tid; i < QQ; i += NT) {
             const int t1 = i / Q, t2 = i - t1 * Q;
-            cpx<T> o[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                cpx<T> acc = {(T)0, (T)0};
-#pragma unroll
-                for (int c1 = 0; c1 < 2; ++c1) {
-                    const T *m = Ms + c1 * QQ + t1 * Q;
-#pragma unroll
-                    for (int tp1 = 0; tp1 < Q; ++tp1) crfma(acc, m[tp1], W[k][c1 * QQ + tp1 * Q + t2]);
-                }
-                o[k] = acc;
-            }
             const G3 gg = Gb[t2];
-            const cpx<T> e = cis<T>(rb[t1] * gg.g);
-            const cpx<T> o0 = cmulc(o[0], e);
-            dst[i] = o0;
-            dst[plane + i] = csub(cmulc(o[1], e), i2pi(rb[t1] * gg.d1, o0));
-            dst[2 * plane + i] = csub(cmulc(o[2], e), i2pi(rb[t1] * gg.d2, o0));
+            Er[j][i] = cis<T>(rb[t1] * gg.g);
+            Sr[0][j][i] = (T)(TWO_PI * (rb[t1] * gg.d1));
+            Sr[1][j][i] = (T)(TWO_PI * (rb[t1] * gg.d2));
         }
         __syncthreads();
+    }
+    // the two contractions go row by row: a thread loads one row of its
+    // operand into registers once and makes a run of outputs from it, with
+    // the interpolation matrix read through the scalar cache (wave-uniform
+    // offsets).  Pass 1, rows (k, c1, t'1), outputs t2 in half (w & 1);
+    // pass 2, rows (k, t2), outputs t1 in quarter w.
+    constexpr int HA = (Q + 1) / 2, HB = (Q + 3) / 4, NPT = (4 * QQ + NT - 1) / NT;
+    cptr<T> Mg = to_constant(pick_M<T>(tb));
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    // a thread's share of the block's three input planes sits in registers,
+    // the next right-hand side's loads in flight while this one computes
+    cpx<T> xin[3][NPT], xnx[3][NPT];
+    fetch_planes<T, 4 * QQ>(xin, win + blk * (4 * QQ), plane, tid);
+    for (int r = 0; r < nrhs; ++r) {
+        fetch_planes<T, 4 * QQ>(xnx, win + (size_t)min(r + 1, nrhs - 1) * rstride + blk * (4 * QQ), plane, tid);
+        for (int j = 0; j < 4; ++j) {
+            opaque_sgpr(Mg);
+#pragma unroll
+            for (int n = 0; n < NPT; ++n) {
+                const int i = tid + n * NT;
+                if (i < 4 * QQ) {
+                    const cpx<T> e = Ep[j][i];
+                    const cpx<T> in0 = xin[0][n];
+                    const T s1 = Sp[0][j][i], s2 = Sp[1][j][i];
+                    v[0][i] = cmul(e, in0);
+                    v[1][i] = cmul(e, cadd(xin[1][n], cpx<T>{-s1 * in0.im, s1 * in0.re}));
+                    v[2][i] = cmul(e, cadd(xin[2][n], cpx<T>{-s2 * in0.im, s2 * in0.re}));
+                }
+            }
+            __syncthreads();
+            // W[k][c1][t'1][t2] = sum_{c2, t'2} M_c2[t2][t'2] v[k][2 c1 + c2][t'1][t'2]
+            with_uniform<0, 2>(w & 1, [&](auto hc) {
+                constexpr int t0 = decltype(hc)::value * HA, nt = Q - t0 < HA ? Q - t0 : HA;
+                for (int row = (w >> 1) * 64 + lane; row < 6 * Q; row += 128) {
+                    const int k = row / (2 * Q), rem = row - k * 2 * Q;
+                    const int c1 = rem / Q, tp1 = rem - c1 * Q;
+                    cpx<T> acc[nt];
+#pragma unroll
+                    for (int u = 0; u < nt; ++u) acc[u] = {(T)0, (T)0};
+#pragma unroll
+                    for (int c2 = 0; c2 < 2; ++c2) {
+                        const cpx<T> *vv = v[k] + (2 * c1 + c2) * QQ + tp1 * Q;
+#pragma unroll
+                        for (int tp2 = 0; tp2 < Q; ++tp2) {
+                            const cpx<T> x = vv[tp2];
+#pragma unroll
+                            for (int u = 0; u < nt; ++u) crfma(acc[u], Mg[c2 * QQ + (t0 + u) * Q + tp2], x);
+                        }
+                    }
+                    cpx<T> *ww = W[k] + c1 * QQ + tp1 * Q + t0;
+#pragma unroll
+                    for (int u = 0; u < nt; ++u) ww[u] = acc[u];
+                }
+            });
+            __syncthreads();
+            // o[k][t1][t2] = sum_{c1, t'1} M_c1[t1][t'1] W[k][c1][t'1][t2], into v[k][0, QQ)
+            with_uniform<0, 4>(w, [&](auto pc) {
+                constexpr int t0 = decltype(pc)::value * HB;
+                constexpr int nt = Q - t0 >= HB ? HB : (Q - t0 > 0 ? Q - t0 : 0);
+                if constexpr (nt > 0) {
+                    if (lane < 3 * Q) {
+                        const int k = lane / Q, t2 = lane - k * Q;
+                        cpx<T> acc[nt];
+#pragma unroll
+                        for (int u = 0; u < nt; ++u) acc[u] = {(T)0, (T)0};
+#pragma unroll
+                        for (int c1 = 0; c1 < 2; ++c1) {
+#pragma unroll
+                            for (int tp1 = 0; tp1 < Q; ++tp1) {
+                                const cpx<T> x = W[k][c1 * QQ + tp1 * Q + t2];
+#pragma unroll
+                                for (int u = 0; u < nt; ++u) crfma(acc[u], Mg[c1 * QQ + (t0 + u) * Q + tp1], x);
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < nt; ++u) v[k][(t0 + u) * Q + t2] = acc[u];
+                    }
+                }
+            });
+            __syncthreads();
+            cpx<T> *dst = wout + r * rstride + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
+            for (int i = tid; i < QQ; i += NT) {
+                const cpx<T> e = Er[j][i];
+                const cpx<T> o0 = cmulc(v[0][i], e);
+                const T s1 = Sr[0][j][i], s2 = Sr[1][j][i];
+                dst[i] = o0;
+                dst[plane + i] = csub(cmulc(v[1][i], e), cpx<T>{-s1 * o0.im, s1 * o0.re});
+                dst[2 * plane + i] = csub(cmulc(v[2][i], e), cpx<T>{-s2 * o0.im, s2 * o0.re});
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int n = 0; n < NPT; ++n) xin[k][n] = xnx[k][n];
     }
 }
 
@@ -374,17 +455,25 @@ __global__ __launch_bounds__(NT) void k_switch_tan(Geom g, PhaseDev ph, Tables t
 // x-recursion (eq:alg2c) with derivatives, one workgroup per block:
 //   v   = conj Ep . in,  d v = conj Ep . (d in - 2 pi i dPhi_p . in)
 //   out = sum_c Er_c . z_c, z_c = K_A v_c;  d out = sum_c Er_c . (d z_c + 2 pi i dPhi_r,c . z_c)
+// The kernel values (Ep of the inputs, Er of the four outputs, and the
+// factors 2 pi dPhi of the derivative terms) are made once per block in LDS
+// and serve nrhs right-hand sides, whose three planes start rstride apart.
 // ===========================================================================
 template <typename T, int Q>
 __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables tb, int level,
                                                    const cpx<T> *__restrict__ win,
-                                                   cpx<T> *__restrict__ wout, size_t plane) {
+                                                   cpx<T> *__restrict__ wout, size_t plane, int nrhs,
+                                                   size_t rstride) {
     constexpr int QQ = Q * Q;
+    constexpr double TWO_PI = 6.283185307179586476925286766559;
     __shared__ cpx<T> v[3][4 * QQ];
     __shared__ cpx<T> Y[3][4 * QQ];
-    __shared__ T Ms[2 * QQ];
     __shared__ double sx1[Q], cx1[Q], sx2[Q], cx2[Q];
     __shared__ double r0c[2], ct0[2], st0[2];
+    __shared__ cpx<T> Ep[4 * QQ];       // E(x^{A_p}_t', p0(B_c)) [c][t']
+    __shared__ T Sp[2][4 * QQ];         // 2 pi rho dPhi_k of the same
+    __shared__ cpx<T> Er[4][4][QQ];    // E(x^{A_j}_t, p0(B_c)) [j][c][t]
+    __shared__ T Sr[2][4][4][QQ];
 
     const int tid = threadIdx.x;
     const int lB = g.L - level;
@@ -397,8 +486,6 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
     morton_decode(mAp, ap1, ap2);
     const bool ell = ph.kind == FIO_PHASE_ELLIPSE;
 
-    const T *Mg = pick_M<T>(tb);
-    for (int i = tid; i < 2 * QQ; i += NT) Ms[i] = Mg[i];
     if (tid < 2) {
         r0c[tid] = g.rho_scale * box_centre(2 * b1 + tid, lB + 1);
         double s_, c_;
@@ -419,7 +506,7 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
         cx2[t] = c_;
     }
     __syncthreads();
-    const cpx<T> *src = win + blk * (4 * QQ);
+    // prefactor kernel values of the inputs
     for (int i = tid; i < 2 * QQ; i += NT) {
         const int c2 = i / QQ, tp = i - c2 * QQ;
         const int tp1 = tp / Q, tp2 = tp - tp1 * Q;
@@ -430,14 +517,13 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
         for (int c1 = 0; c1 < 2; ++c1) {
             const int c = 2 * c1 + c2;
             const double rho = r0c[c1];
-            const cpx<T> e = cis<T>(rho * G.g);
-            const cpx<T> in0 = src[c * QQ + tp];
-            v[0][c * QQ + tp] = cmulc(in0, e);
-            v[1][c * QQ + tp] = cmulc(csub(src[plane + c * QQ + tp], i2pi(rho * G.d1, in0)), e);
-            v[2][c * QQ + tp] = cmulc(csub(src[2 * plane + c * QQ + tp], i2pi(rho * G.d2, in0)), e);
+            Ep[c * QQ + tp] = cis<T>(rho * G.g);
+            Sp[0][c * QQ + tp] = (T)(TWO_PI * (rho * G.d1));
+            Sp[1][c * QQ + tp] = (T)(TWO_PI * (rho * G.d2));
         }
     }
     __syncthreads();
+    // remodulation kernel values of output j into table slot sl
     for (int j = 0; j < 4; ++j) {
         const int j1 = j >> 1, j2 = j & 1;
         const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
@@ -453,49 +539,115 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
             sx2[t] = s_;
             cx2[t] = c_;
         }
-        for (int i = tid; i < 3 * 4 * QQ; i += NT) {
-            const int k = i / (4 * QQ), ii = i - k * 4 * QQ;
-            const int c = ii / QQ, r = ii - c * QQ;
-            const int tp1 = r / Q, t2 = r - tp1 * Q;
-            const cpx<T> *vv = v[k] + c * QQ + tp1 * Q;
-            const T *m = Ms + j2 * QQ + t2;
-            cpx<T> acc = {(T)0, (T)0};
-#pragma unroll
-            for (int tp2 = 0; tp2 < Q; ++tp2) crfma(acc, m[tp2 * Q], vv[tp2]);
-            Y[k][ii] = acc;
-        }
         __syncthreads();
-        cpx<T> *dst = wout + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
         for (int i = tid; i < QQ; i += NT) {
             const int t1 = i / Q, t2 = i - t1 * Q;
             const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[t2]), sx1[t1],
                                      cx1[t1], sx2[t2], cx2[t2]);
             const G3 G0 = phase_dir3(xp, ph, ct0[0], st0[0]);
             const G3 G1 = phase_dir3(xp, ph, ct0[1], st0[1]);
-            cpx<T> out[3] = {{(T)0, (T)0}, {(T)0, (T)0}, {(T)0, (T)0}};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int c1 = c >> 1, c2 = c & 1;
-                const T *m = Ms + j1 * QQ + t1;
-                cpx<T> z[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    cpx<T> acc = {(T)0, (T)0};
-#pragma unroll
-                    for (int tp1 = 0; tp1 < Q; ++tp1) crfma(acc, m[tp1 * Q], Y[k][c * QQ + tp1 * Q + t2]);
-                    z[k] = acc;
-                }
                 const G3 &G = c2 ? G1 : G0;
                 const double rho = r0c[c1];
-                const cpx<T> e = cis<T>(rho * G.g);
-                cfma(out[0], e, z[0]);
-                cfma(out[1], e, cadd(z[1], i2pi(rho * G.d1, z[0])));
-                cfma(out[2], e, cadd(z[2], i2pi(rho * G.d2, z[0])));
+                Er[j][c][i] = cis<T>(rho * G.g);
+                Sr[0][j][c][i] = (T)(TWO_PI * (rho * G.d1));
+                Sr[1][j][c][i] = (T)(TWO_PI * (rho * G.d2));
             }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) dst[k * plane + i] = out[k];
         }
         __syncthreads();
+    }
+    // the two contractions go row by row (a thread loads one row of its
+    // operand into registers once, the interpolation matrix comes through
+    // the scalar cache): pass 1, rows (k, c, t'1), outputs t2 in half (w & 1);
+    // pass 2 in place, one thread per column (k, c, t2), all t1.
+    constexpr int HA = (Q + 1) / 2, NPT = (4 * QQ + NT - 1) / NT;
+    cptr<T> Mg = to_constant(pick_M<T>(tb));
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    // the next right-hand side's inputs load into registers while this one computes
+    cpx<T> xin[3][NPT], xnx[3][NPT];
+    fetch_planes<T, 4 * QQ>(xin, win + blk * (4 * QQ), plane, tid);
+    for (int r = 0; r < nrhs; ++r) {
+        fetch_planes<T, 4 * QQ>(xnx, win + (size_t)min(r + 1, nrhs - 1) * rstride + blk * (4 * QQ), plane, tid);
+#pragma unroll
+        for (int n = 0; n < NPT; ++n) {
+            const int i = tid + n * NT;
+            if (i < 4 * QQ) {
+                const cpx<T> e = Ep[i];
+                const cpx<T> in0 = xin[0][n];
+                const T s1 = Sp[0][i], s2 = Sp[1][i];
+                v[0][i] = cmulc(in0, e);
+                v[1][i] = cmulc(csub(xin[1][n], cpx<T>{-s1 * in0.im, s1 * in0.re}), e);
+                v[2][i] = cmulc(csub(xin[2][n], cpx<T>{-s2 * in0.im, s2 * in0.re}), e);
+            }
+        }
+        __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+            const int j1 = j >> 1, j2 = j & 1;
+            opaque_sgpr(Mg);
+            // Y[k][c][t'1][t2] = sum_{t'2} M_j2[t'2][t2] v[k][c][t'1][t'2]
+            with_uniform<0, 2>(w & 1, [&](auto hc) {
+                constexpr int t0 = decltype(hc)::value * HA, nt = Q - t0 < HA ? Q - t0 : HA;
+                for (int row = (w >> 1) * 64 + lane; row < 12 * Q; row += 128) {
+                    const int k = row / (4 * Q), rem = row - k * 4 * Q;
+                    const int c = rem / Q, tp1 = rem - c * Q;
+                    const cpx<T> *vv = v[k] + c * QQ + tp1 * Q;
+                    cpx<T> acc[nt];
+#pragma unroll
+                    for (int u = 0; u < nt; ++u) acc[u] = {(T)0, (T)0};
+#pragma unroll
+                    for (int tp2 = 0; tp2 < Q; ++tp2) {
+                        const cpx<T> x = vv[tp2];
+#pragma unroll
+                        for (int u = 0; u < nt; ++u) crfma(acc[u], Mg[j2 * QQ + tp2 * Q + t0 + u], x);
+                    }
+                    cpx<T> *yy = Y[k] + c * QQ + tp1 * Q + t0;
+#pragma unroll
+                    for (int u = 0; u < nt; ++u) yy[u] = acc[u];
+                }
+            });
+            __syncthreads();
+            // z[k][c][t1][t2] = sum_{t'1} M_j1[t'1][t1] Y[k][c][t'1][t2], in place
+            for (int row = tid; row < 12 * Q; row += NT) {
+                const int k = row / (4 * Q), rem = row - k * 4 * Q;
+                const int c = rem / Q, t2 = rem - c * Q;
+                cpx<T> *yy = Y[k] + c * QQ + t2;
+                cpx<T> x[Q];
+#pragma unroll
+                for (int tp1 = 0; tp1 < Q; ++tp1) x[tp1] = yy[tp1 * Q];
+                cptr<T> Mj = Mg + j1 * QQ;
+#pragma unroll
+                for (int t1 = 0; t1 < Q; ++t1) {
+                    opaque_sgpr(Mj);  // one column of M live at a time
+                    cpx<T> acc = {(T)0, (T)0};
+#pragma unroll
+                    for (int tp1 = 0; tp1 < Q; ++tp1) crfma(acc, Mj[tp1 * Q + t1], x[tp1]);
+                    yy[t1 * Q] = acc;
+                }
+            }
+            __syncthreads();
+            cpx<T> *dst = wout + r * rstride + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
+            for (int i = tid; i < QQ; i += NT) {
+                cpx<T> out[3] = {{(T)0, (T)0}, {(T)0, (T)0}, {(T)0, (T)0}};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const cpx<T> z0 = Y[0][c * QQ + i], z1 = Y[1][c * QQ + i], z2 = Y[2][c * QQ + i];
+                    const cpx<T> e = Er[j][c][i];
+                    const T s1 = Sr[0][j][c][i], s2 = Sr[1][j][c][i];
+                    cfma(out[0], e, z0);
+                    cfma(out[1], e, cadd(z1, cpx<T>{-s1 * z0.im, s1 * z0.re}));
+                    cfma(out[2], e, cadd(z2, cpx<T>{-s2 * z0.im, s2 * z0.re}));
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dst[k * plane + i] = out[k];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int n = 0; n < NPT; ++n) xin[k][n] = xnx[k][n];
     }
 }
 
@@ -643,7 +795,7 @@ bool tangent_supported_q(int q) { return q >= QMIN && q <= 12; }
 
 template <typename T>
 static hipError_t tan_t(int step, const Geom &g, const PhaseDev &ph, const Tables &tb, const Sources &src,
-                        int level, const void *in, void *out, size_t plane, void *u1, void *u2,
+                        int level, const void *in, void *out, size_t plane, void *u1, void *u2, int nrhs,
                         hipStream_t st) {
     if (step == 0) {
         const unsigned nB = 1u << (2 * (g.L - g.s));
@@ -661,10 +813,10 @@ static hipError_t tan_t(int step, const Geom &g, const PhaseDev &ph, const Table
 #define L_LT(Q)                                                                                          \
     if (step == 1)                                                                                       \
         hipLaunchKernelGGL((k_plevel_tan<T, Q>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, level,       \
-                           (const cpx<T> *)in, (cpx<T> *)out, plane);                                    \
+                           (const cpx<T> *)in, (cpx<T> *)out, plane, nrhs, 3 * plane);                   \
     else                                                                                                 \
         hipLaunchKernelGGL((k_xlevel_tan<T, Q>), grid_of(nblk), dim3(NT), 0, st, g, ph, tb, level,       \
-                           (const cpx<T> *)in, (cpx<T> *)out, plane);
+                           (const cpx<T> *)in, (cpx<T> *)out, plane, nrhs, 3 * plane);
         FIO_DISPATCH_QT(g.q, L_LT)
 #undef L_LT
     } else if (step == 2) {
@@ -690,9 +842,9 @@ static hipError_t tan_t(int step, const Geom &g, const PhaseDev &ph, const Table
 
 hipError_t launch_tangent_step(int dtype, int step, const Geom &g, const PhaseDev &ph, const Tables &tb,
                                const Sources &src, int level, const void *in, void *out, size_t plane,
-                               void *u1, void *u2, hipStream_t st) {
-    return dtype == FIO_C128 ? tan_t<double>(step, g, ph, tb, src, level, in, out, plane, u1, u2, st)
-                             : tan_t<float>(step, g, ph, tb, src, level, in, out, plane, u1, u2, st);
+                               void *u1, void *u2, int nrhs, hipStream_t st) {
+    return dtype == FIO_C128 ? tan_t<double>(step, g, ph, tb, src, level, in, out, plane, u1, u2, nrhs, st)
+                             : tan_t<float>(step, g, ph, tb, src, level, in, out, plane, u1, u2, nrhs, st);
 }
 
 }  // namespace fio

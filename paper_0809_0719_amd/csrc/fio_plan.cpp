@@ -730,28 +730,38 @@ static int run_adjoint(fio_plan_t p, const void *u, void *f, int nr, hipStream_t
     return FIO_OK;
 }
 
-// Primal and the two phase tangents of one right-hand side through the
-// whole pass (kernels of fio_kernels_tan.hip).
-static int run_tangent(fio_plan_t p, const void *f, void *u, void *d1, void *d2, hipStream_t st) {
+// Primal and the two phase tangents of nr right-hand sides through the
+// whole pass (kernels of fio_kernels_tan.hip).  Right-hand side r keeps its
+// three weight planes at 3r, 3r + 1 and 3r + 2 of the plan's buffers; the
+// level kernels take all nr in one launch and make their exponentials once,
+// the initialisation, switch and termination go one right-hand side a launch.
+static int run_tangent(fio_plan_t p, const char *f, char *u, char *d1, char *d2, int nr, size_t fstep,
+                       hipStream_t st) {
     const PhaseDev ph = to_dev(&p->phase);
     Sources src{p->d_idx, p->d_p, p->d_off};
     char *a = (char *)(p->nrhs_max >= 3 ? p->w0 : p->t0), *b = (char *)(p->nrhs_max >= 3 ? p->w1 : p->t1);
+    const size_t rb = 3 * p->wbytes;
     Timed tm(p, FIO_K_TANGENT, st);
-    hipError_t e = launch_tangent_step(p->dtype, 0, p->geom, ph, p->tb, src, 0, f, a, p->plane, nullptr,
-                                       nullptr, st);
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < nr && e == hipSuccess; ++r)
+        e = launch_tangent_step(p->dtype, 0, p->geom, ph, p->tb, src, 0, f + r * fstep, a + r * rb, p->plane,
+                                nullptr, nullptr, 1, st);
     for (int l = p->s + 1; l <= p->lm && e == hipSuccess; ++l) {
-        e = launch_tangent_step(p->dtype, 1, p->geom, ph, p->tb, src, l, a, b, p->plane, nullptr, nullptr, st);
-        std::swap(a, b);
-    }
-    if (e == hipSuccess)
-        e = launch_tangent_step(p->dtype, 2, p->geom, ph, p->tb, src, p->lm, a, a, p->plane, nullptr, nullptr,
+        e = launch_tangent_step(p->dtype, 1, p->geom, ph, p->tb, src, l, a, b, p->plane, nullptr, nullptr, nr,
                                 st);
-    for (int l = p->lm + 1; l <= p->L - p->s && e == hipSuccess; ++l) {
-        e = launch_tangent_step(p->dtype, 3, p->geom, ph, p->tb, src, l, a, b, p->plane, nullptr, nullptr, st);
         std::swap(a, b);
     }
-    if (e == hipSuccess)
-        e = launch_tangent_step(p->dtype, 4, p->geom, ph, p->tb, src, 0, a, u, p->plane, d1, d2, st);
+    for (int r = 0; r < nr && e == hipSuccess; ++r)
+        e = launch_tangent_step(p->dtype, 2, p->geom, ph, p->tb, src, p->lm, a + r * rb, a + r * rb, p->plane,
+                                nullptr, nullptr, 1, st);
+    for (int l = p->lm + 1; l <= p->L - p->s && e == hipSuccess; ++l) {
+        e = launch_tangent_step(p->dtype, 3, p->geom, ph, p->tb, src, l, a, b, p->plane, nullptr, nullptr, nr,
+                                st);
+        std::swap(a, b);
+    }
+    for (int r = 0; r < nr && e == hipSuccess; ++r)
+        e = launch_tangent_step(p->dtype, 4, p->geom, ph, p->tb, src, 0, a + r * rb, u ? u + r * fstep : nullptr,
+                                p->plane, d1 + r * fstep, d2 + r * fstep, 1, st);
     if (e != hipSuccess) return hip_fail(e, "tangent launch");
     return FIO_OK;
 }
@@ -784,10 +794,15 @@ int fio_apply_dphase(fio_plan_t plan, const void *f, void *u, void *du_da1, void
         plan->total_bytes = tot;
     }
     const size_t step = (size_t)plan->N * plan->N * (plan->dtype == FIO_C128 ? 16 : 8);
+    // chunks of at most nrhs_max / 3 right-hand sides, as even as they come
+    const int cmax = plan->nrhs_max >= 3 ? plan->nrhs_max / 3 : 1;
+    const int nchunks = (nrhs + cmax - 1) / cmax;
+    const int chunk = (nrhs + nchunks - 1) / nchunks;
     hipStream_t st = (hipStream_t)stream;
-    for (int r = 0; r < nrhs; ++r) {
+    for (int r = 0; r < nrhs; r += chunk) {
+        const int nr = std::min(chunk, nrhs - r);
         rc = run_tangent(plan, (const char *)f + r * step, u ? (char *)u + r * step : nullptr,
-                         (char *)du_da1 + r * step, (char *)du_da2 + r * step, st);
+                         (char *)du_da1 + r * step, (char *)du_da2 + r * step, nr, step, st);
         if (rc) return rc;
     }
     return FIO_OK;

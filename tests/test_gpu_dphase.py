@@ -140,6 +140,35 @@ def test_dphase_several_rhs_and_workspace_reuse(dtype):
     assert rel_max(u4.cpu().numpy(), p4.apply(f).cpu().numpy()) <= tol
 
 
+@pytest.mark.parametrize("dtype,N,q,s", [(torch.complex64, 64, 9, 1), (torch.complex128, 64, 9, 1),
+                                          (torch.complex64, 32, 12, 1), (torch.complex128, 32, 12, 1)])
+def test_dphase_batched_levels_equal_one_at_a_time(dtype, N, q, s):
+    """A plan with nrhs_max = 9 takes the tangent in chunks of three right-hand
+    sides (three weight planes each); seven of them (chunks 3, 3, 1) through
+    the batched level kernels give bit for bit what one at a time gives, with
+    two p-levels and two x-levels on the path."""
+    ph = D.Phase(a1=1.1, a2=0.85, eta1=0.2)
+    f = _dev(white_noise(N, 21, nrhs=7), dtype)
+    p9 = _plan(N, q, ph, s, None, dtype, nrhs_max=9)
+    p1 = _plan(N, q, ph, s, None, dtype, nrhs_max=1)
+    u9, b1, b2 = p9.apply_dphase(f)
+    for r in range(7):
+        u, c1, c2 = p1.apply_dphase(f[r])
+        assert torch.equal(u, u9[r]) and torch.equal(c1, b1[r]) and torch.equal(c2, b2[r]), r
+    # and the chunked pass is right, not only self-consistent: the last
+    # right-hand side (a chunk of one) against the oracle's difference quotients
+    fr = white_noise(N, 21, nrhs=7)[6]
+    ref = []
+    for name in ("a1", "a2"):
+        a, h = getattr(ph, name), 1e-6
+        up = ButterflyModel(N, q, _with(ph, **{name: a * (1 + h)}), s=s).apply(fr)
+        um = ButterflyModel(N, q, _with(ph, **{name: a * (1 - h)}), s=s).apply(fr)
+        ref.append((up - um) / (2 * a * h))
+    errs = [rel_l2(b1[6].cpu().numpy(), ref[0]), rel_l2(b2[6].cpu().numpy(), ref[1])]
+    print(f"batched dphase {dtype} N={N} q={q}: d/da1 {errs[0]:.2e} d/da2 {errs[1]:.2e}")
+    assert max(errs) <= (FD_TOL if dtype == torch.complex128 else FP32_TOL)
+
+
 def test_dphase_bad_arguments():
     import paper_0809_0719_amd as fio
     N = 16
