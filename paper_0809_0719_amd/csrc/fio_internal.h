@@ -155,8 +155,8 @@ hipError_t launch_init_adj(int dtype, const Geom &g, const PhaseDev &ph, const T
 // three planes `plane` complex values apart (primal, d/da1, d/da2).  `step`:
 // 0 initialisation (in = f), 1 p-level, 2 switch (in place on out),
 // 3 x-level, 4 termination (out = u or NULL, u1 = du/da1, u2 = du/da2).
-// The level steps (1, 3) take `nrhs` right-hand sides whose planes start
-// 3 * plane apart; the others take one and ignore `nrhs`.
+// The level and switch steps (1, 2, 3) take `nrhs` right-hand sides whose
+// planes start 3 * plane apart; the others take one and ignore `nrhs`.
 bool tangent_supported_q(int q);
 hipError_t launch_tangent_step(int dtype, int step, const Geom &g, const PhaseDev &ph, const Tables &tb,
                                const Sources &src, int level, const void *in, void *out, size_t plane,

@@ -354,13 +354,21 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
 // With the same node symmetry as the forward switch; the derivative term
 // uses the weighted plane in'(s) = rho(s1) in(s).
 // ===========================================================================
-template <typename T, int Q>
+template <typename T, int Q, bool HOLD>
 __global__ __launch_bounds__(NT) void k_switch_tan(Geom g, PhaseDev ph, Tables tb, cpx<T> *__restrict__ w,
-                                                   size_t plane) {
+                                                   size_t plane, int nrhs, size_t rstride) {
     constexpr int QQ = Q * Q;
     constexpr int H = Q / 2;
     constexpr int HH = H > 0 ? H : 1;
     constexpr int PPB = NT / QQ;
+    constexpr double TWO_PI = 6.283185307179586476925286766559;
+    // HOLD (FP32, a chunk of right-hand sides): a thread's kernel values
+    // against every s2 stay in registers for the whole chunk and the next
+    // right-hand side's inputs load while this one computes.  Otherwise
+    // (one right-hand side, or FP64, whose tables would not fit) the values
+    // are made again for each right-hand side, with fewer registers.
+    static_assert(!HOLD || sizeof(T) == 4, "register-held tables are FP32 only");
+    constexpr int NS = HOLD ? Q : 1;
     __shared__ cpx<T> Sx[PPB][4][Q][HH];
     __shared__ cpx<T> Dx[PPB][4][Q][HH];
     __shared__ cpx<T> Mid[PPB][4][Q];
@@ -380,7 +388,6 @@ __global__ __launch_bounds__(NT) void k_switch_tan(Geom g, PhaseDev ph, Tables t
     morton_decode(mB, b1, b2);
     morton_decode(mA, a1, a2);
     const int t1 = t / Q, t2 = t - t1 * Q;
-    cpx<T> *wp = w + pair * QQ;
 
     if (active) {
         if (t < Q) {
@@ -396,59 +403,123 @@ __global__ __launch_bounds__(NT) void k_switch_tan(Geom g, PhaseDev ph, Tables t
         }
     }
     __syncthreads();
+    XP xp{};
+    double r0 = 0.0;
+    cpx<T> base[NS], d[NS][HH];
+    T f1[NS], f2[NS];
     if (active) {
-        // planes 0, 1, 2 and the weighted primal rho(s1) in0(s); thread (t1, t2): t1 plays j
-        if (t1 < H) {
-            const double ra = rhos[pl][t1], rbv = rhos[pl][Q - 1 - t1];
+        xp = make_xp(ph, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]));
+        r0 = rho0[pl];
+        if constexpr (HOLD) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const size_t off = (k < 3 ? k : 0) * plane;
-                cpx<T> a = wp[off + t1 * Q + t2], b = wp[off + (Q - 1 - t1) * Q + t2];
-                if (k == 3) {
-                    a = {(T)(ra * a.re), (T)(ra * a.im)};
-                    b = {(T)(rbv * b.re), (T)(rbv * b.im)};
+            for (int s2 = 0; s2 < Q; ++s2) {
+                const G3 G = phase_dir3(xp, ph, cth[pl][s2], sth[pl][s2]);
+                base[s2] = cis<T>(r0 * G.g);
+#pragma unroll
+                for (int j = 0; j < H; ++j) d[s2][j] = cis<T>(hz[pl][j] * G.g);
+                f1[s2] = (T)(TWO_PI * G.d1);
+                f2[s2] = (T)(TWO_PI * G.d2);
+            }
+        }
+    }
+    // rows t1 and Q - 1 - t1 of the three planes at (., t2), every active
+    // thread (the rows of t1 >= H are loaded and not used: in bounds)
+    constexpr int NA = HOLD ? 3 : 1;
+    cpx<T> A[NA], B[NA], An[NA], Bn[NA];
+    auto fetch = [&](cpx<T> (&a)[NA], cpx<T> (&b)[NA], int r) __attribute__((always_inline)) {
+        const cpx<T> *wp = w + r * rstride + pair * QQ;
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            a[k] = wp[k * plane + t1 * Q + t2];
+            b[k] = wp[k * plane + (Q - 1 - t1) * Q + t2];
+        }
+    };
+    if constexpr (HOLD)
+        if (active) fetch(A, B, 0);
+    for (int r = 0; r < nrhs; ++r) {
+        cpx<T> *wp = w + r * rstride + pair * QQ;
+        if constexpr (HOLD)
+            if (active) fetch(An, Bn, min(r + 1, nrhs - 1));
+        if (active) {
+            // planes 0, 1, 2 and the weighted primal rho(s1) in0(s); thread (t1, t2): t1 plays j
+            if (t1 < H) {
+                const double ra = rhos[pl][t1], rbv = rhos[pl][Q - 1 - t1];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const size_t off = (k < 3 ? k : 0) * plane;
+                    cpx<T> a, b;
+                    if constexpr (HOLD) {
+                        a = A[k < 3 ? k : 0];
+                        b = B[k < 3 ? k : 0];
+                    } else {
+                        a = wp[off + t1 * Q + t2];
+                        b = wp[off + (Q - 1 - t1) * Q + t2];
+                    }
+                    if (k == 3) {
+                        a = {(T)(ra * a.re), (T)(ra * a.im)};
+                        b = {(T)(rbv * b.re), (T)(rbv * b.im)};
+                    }
+                    Sx[pl][k][t2][t1] = cadd(a, b);
+                    Dx[pl][k][t2][t1] = csub(a, b);
                 }
-                Sx[pl][k][t2][t1] = cadd(a, b);
-                Dx[pl][k][t2][t1] = csub(a, b);
-            }
-        } else if ((Q & 1) && t1 == H) {
-            const double rm = rhos[pl][H];
+            } else if ((Q & 1) && t1 == H) {
+                const double rm = rhos[pl][H];
+                if constexpr (HOLD) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) Mid[pl][k][t2] = wp[k * plane + H * Q + t2];
-            const cpx<T> a = wp[H * Q + t2];
-            Mid[pl][3][t2] = {(T)(rm * a.re), (T)(rm * a.im)};
+                    for (int k = 0; k < 3; ++k) Mid[pl][k][t2] = A[k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) Mid[pl][k][t2] = wp[k * plane + H * Q + t2];
+                }
+                const cpx<T> a = Mid[pl][0][t2];
+                Mid[pl][3][t2] = {(T)(rm * a.re), (T)(rm * a.im)};
+            }
         }
-    }
-    __syncthreads();
-    if (!active) return;
-    const XP xp = make_xp(ph, box_node(a1, lA, tb.z[t1]), box_node(a2, lA, tb.z[t2]));
-    const double r0 = rho0[pl];
-    cpx<T> acc[3] = {{(T)0, (T)0}, {(T)0, (T)0}, {(T)0, (T)0}};
+        __syncthreads();
+        if (active) {
+            cpx<T> acc[3] = {{(T)0, (T)0}, {(T)0, (T)0}, {(T)0, (T)0}};
+            auto step = [&](int s2, const cpx<T> &bs, const cpx<T> *ds, T g1, T g2) __attribute__((always_inline)) {
+                cpx<T> inner[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    cpx<T> in = (Q & 1) ? Mid[pl][k][s2] : cpx<T>{(T)0, (T)0};
+#pragma unroll
+                    for (int j = 0; j < H; ++j) {
+                        const cpx<T> S = Sx[pl][k][s2][j], D = Dx[pl][k][s2][j];
+                        in.re = fma(ds[j].re, S.re, fma(-ds[j].im, D.im, in.re));
+                        in.im = fma(ds[j].re, S.im, fma(ds[j].im, D.re, in.im));
+                    }
+                    inner[k] = in;
+                }
+                cfma(acc[0], bs, inner[0]);
+                cfma(acc[1], bs, cadd(inner[1], cpx<T>{-g1 * inner[3].im, g1 * inner[3].re}));
+                cfma(acc[2], bs, cadd(inner[2], cpx<T>{-g2 * inner[3].im, g2 * inner[3].re}));
+            };
+            if constexpr (HOLD) {
+#pragma unroll
+                for (int s2 = 0; s2 < Q; ++s2) step(s2, base[s2], d[s2], f1[s2], f2[s2]);
+            } else {
 #pragma unroll 1
-    for (int s2 = 0; s2 < Q; ++s2) {
-        const G3 G = phase_dir3(xp, ph, cth[pl][s2], sth[pl][s2]);
-        const cpx<T> base = cis<T>(r0 * G.g);
-        cpx<T> d[HH];
+                for (int s2 = 0; s2 < Q; ++s2) {
+                    const G3 G = phase_dir3(xp, ph, cth[pl][s2], sth[pl][s2]);
+                    cpx<T> dd[HH];
 #pragma unroll
-        for (int j = 0; j < H; ++j) d[j] = cis<T>(hz[pl][j] * G.g);
-        cpx<T> inner[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            cpx<T> in = (Q & 1) ? Mid[pl][k][s2] : cpx<T>{(T)0, (T)0};
-#pragma unroll
-            for (int j = 0; j < H; ++j) {
-                const cpx<T> S = Sx[pl][k][s2][j], D = Dx[pl][k][s2][j];
-                in.re = fma(d[j].re, S.re, fma(-d[j].im, D.im, in.re));
-                in.im = fma(d[j].re, S.im, fma(d[j].im, D.re, in.im));
+                    for (int j = 0; j < H; ++j) dd[j] = cis<T>(hz[pl][j] * G.g);
+                    step(s2, cis<T>(r0 * G.g), dd, (T)(TWO_PI * G.d1), (T)(TWO_PI * G.d2));
+                }
             }
-            inner[k] = in;
-        }
-        cfma(acc[0], base, inner[0]);
-        cfma(acc[1], base, cadd(inner[1], i2pi(G.d1, inner[3])));
-        cfma(acc[2], base, cadd(inner[2], i2pi(G.d2, inner[3])));
-    }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) wp[k * plane + t] = acc[k];
+            for (int k = 0; k < 3; ++k) wp[k * plane + t] = acc[k];
+        }
+        __syncthreads();
+        if constexpr (HOLD) {
+#pragma unroll
+            for (int k = 0; k < NA; ++k) {
+                A[k] = An[k];
+                B[k] = Bn[k];
+            }
+        }
+    }
 }
 
 // ===========================================================================
@@ -824,8 +895,12 @@ static hipError_t tan_t(int step, const Geom &g, const PhaseDev &ph, const Table
 #define L_ST(Q)                                                                                          \
     {                                                                                                    \
         constexpr int PPB = NT / (Q * Q);                                                                \
-        hipLaunchKernelGGL((k_switch_tan<T, Q>), grid_of((npairs + PPB - 1) / PPB), dim3(NT), 0,         \
-                           st, g, ph, tb, (cpx<T> *)out, plane);                                         \
+        if (sizeof(T) == 4 && nrhs > 1)                                                                  \
+            hipLaunchKernelGGL((k_switch_tan<T, Q, sizeof(T) == 4>), grid_of((npairs + PPB - 1) / PPB),  \
+                               dim3(NT), 0, st, g, ph, tb, (cpx<T> *)out, plane, nrhs, 3 * plane);       \
+        else                                                                                             \
+            hipLaunchKernelGGL((k_switch_tan<T, Q, false>), grid_of((npairs + PPB - 1) / PPB), dim3(NT), \
+                               0, st, g, ph, tb, (cpx<T> *)out, plane, nrhs, 3 * plane);                 \
     }
         FIO_DISPATCH_QT(g.q, L_ST)
 #undef L_ST

@@ -733,8 +733,9 @@ static int run_adjoint(fio_plan_t p, const void *u, void *f, int nr, hipStream_t
 // Primal and the two phase tangents of nr right-hand sides through the
 // whole pass (kernels of fio_kernels_tan.hip).  Right-hand side r keeps its
 // three weight planes at 3r, 3r + 1 and 3r + 2 of the plan's buffers; the
-// level kernels take all nr in one launch and make their exponentials once,
-// the initialisation, switch and termination go one right-hand side a launch.
+// level and switch kernels take all nr in one launch and make their kernel
+// values once, the initialisation and termination go one right-hand side a
+// launch.
 static int run_tangent(fio_plan_t p, const char *f, char *u, char *d1, char *d2, int nr, size_t fstep,
                        hipStream_t st) {
     const PhaseDev ph = to_dev(&p->phase);
@@ -751,9 +752,9 @@ static int run_tangent(fio_plan_t p, const char *f, char *u, char *d1, char *d2,
                                 st);
         std::swap(a, b);
     }
-    for (int r = 0; r < nr && e == hipSuccess; ++r)
-        e = launch_tangent_step(p->dtype, 2, p->geom, ph, p->tb, src, p->lm, a + r * rb, a + r * rb, p->plane,
-                                nullptr, nullptr, 1, st);
+    if (e == hipSuccess)
+        e = launch_tangent_step(p->dtype, 2, p->geom, ph, p->tb, src, p->lm, a, a, p->plane, nullptr, nullptr, nr,
+                                st);
     for (int l = p->lm + 1; l <= p->L - p->s && e == hipSuccess; ++l) {
         e = launch_tangent_step(p->dtype, 3, p->geom, ph, p->tb, src, l, a, b, p->plane, nullptr, nullptr, nr,
                                 st);
