@@ -190,7 +190,7 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
     __shared__ cpx<T> W[3][2 * QQ];
     __shared__ double rc[2 * Q], ctc[2 * Q], stc[2 * Q];
     __shared__ double rb[Q], ctb[Q], stb[Q];
-    __shared__ G3 Gc[2 * Q], Gb[Q];
+    __shared__ G3 Gc[4][2 * Q], Gb[4][Q];
     __shared__ cpx<T> Ep[4][4 * QQ];  // E(x0(A_j), p^{B_c}_t')
     __shared__ T Sp[2][4][4 * QQ];    // 2 pi rho dPhi_k(x0(A_j), .) at p^{B_c}_t'
     __shared__ cpx<T> Er[4][QQ];      // E(x0(A_j), p^B_t)
@@ -224,32 +224,37 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
         stb[t] = s_;
     }
     __syncthreads();
-    // kernel values of output j into table slot sl
-    for (int j = 0; j < 4; ++j) {
+    // kernel values of the four outputs, all four at once
+    for (int it = tid; it < 4 * 3 * Q; it += NT) {
+        const int j = it / (3 * Q), u = it - j * (3 * Q);
         const int a1 = 2 * ap1 + (j >> 1), a2 = 2 * ap2 + (j & 1);
         const XP xp = make_xp(ph, box_centre(a1, level), box_centre(a2, level));
-        if (tid < 2 * Q) Gc[tid] = phase_dir3(xp, ph, ctc[tid], stc[tid]);
-        else if (tid >= 64 && tid < 64 + Q) Gb[tid - 64] = phase_dir3(xp, ph, ctb[tid - 64], stb[tid - 64]);
-        __syncthreads();
-        for (int i = tid; i < 4 * QQ; i += NT) {
-            const int c = i / QQ, t = i - c * QQ;
-            const int c1 = c >> 1, c2 = c & 1;
-            const int tp1 = t / Q, tp2 = t - tp1 * Q;
-            const double rho = rc[c1 * Q + tp1];
-            const G3 gg = Gc[c2 * Q + tp2];
-            Ep[j][i] = cis<T>(rho * gg.g);
-            Sp[0][j][i] = (T)(TWO_PI * (rho * gg.d1));
-            Sp[1][j][i] = (T)(TWO_PI * (rho * gg.d2));
-        }
-        for (int i = tid; i < QQ; i += NT) {
-            const int t1 = i / Q, t2 = i - t1 * Q;
-            const G3 gg = Gb[t2];
-            Er[j][i] = cis<T>(rb[t1] * gg.g);
-            Sr[0][j][i] = (T)(TWO_PI * (rb[t1] * gg.d1));
-            Sr[1][j][i] = (T)(TWO_PI * (rb[t1] * gg.d2));
-        }
-        __syncthreads();
+        if (u < 2 * Q)
+            Gc[j][u] = phase_dir3(xp, ph, ctc[u], stc[u]);
+        else
+            Gb[j][u - 2 * Q] = phase_dir3(xp, ph, ctb[u - 2 * Q], stb[u - 2 * Q]);
     }
+    __syncthreads();
+    for (int it = tid; it < 4 * 4 * QQ; it += NT) {
+        const int j = it / (4 * QQ), i = it - j * (4 * QQ);
+        const int c = i / QQ, t = i - c * QQ;
+        const int c1 = c >> 1, c2 = c & 1;
+        const int tp1 = t / Q, tp2 = t - tp1 * Q;
+        const double rho = rc[c1 * Q + tp1];
+        const G3 gg = Gc[j][c2 * Q + tp2];
+        Ep[j][i] = cis<T>(rho * gg.g);
+        Sp[0][j][i] = (T)(TWO_PI * (rho * gg.d1));
+        Sp[1][j][i] = (T)(TWO_PI * (rho * gg.d2));
+    }
+    for (int it = tid; it < 4 * QQ; it += NT) {
+        const int j = it / QQ, i = it - j * QQ;
+        const int t1 = i / Q, t2 = i - t1 * Q;
+        const G3 gg = Gb[j][t2];
+        Er[j][i] = cis<T>(rb[t1] * gg.g);
+        Sr[0][j][i] = (T)(TWO_PI * (rb[t1] * gg.d1));
+        Sr[1][j][i] = (T)(TWO_PI * (rb[t1] * gg.d2));
+    }
+    __syncthreads();
     // the two contractions go row by row: a thread loads one row of its
     // operand into registers once and makes a run of outputs from it, with
     // the interpolation matrix read through the scalar cache (wave-uniform
@@ -540,6 +545,7 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
     __shared__ cpx<T> v[3][4 * QQ];
     __shared__ cpx<T> Y[3][4 * QQ];
     __shared__ double sx1[Q], cx1[Q], sx2[Q], cx2[Q];
+    __shared__ double sxa[2][Q], cxa[2][Q], sxb[2][Q], cxb[2][Q];  // nodes of the children's boxes
     __shared__ double r0c[2], ct0[2], st0[2];
     __shared__ cpx<T> Ep[4 * QQ];       // E(x^{A_p}_t', p0(B_c)) [c][t']
     __shared__ T Sp[2][4 * QQ];         // 2 pi rho dPhi_k of the same
@@ -575,6 +581,18 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
         if (ell) sincospi(2.0 * box_node(ap2, level - 1, tb.z[t]), &s_, &c_);
         sx2[t] = s_;
         cx2[t] = c_;
+    } else if (tid >= 160 && tid < 160 + 4 * Q) {
+        // child boxes 2 ap + h in either coordinate (e = 0: x1, 1: x2)
+        const int u = tid - 160, e = u / (2 * Q), h = (u - e * 2 * Q) / Q, t = u - e * 2 * Q - h * Q;
+        double s_ = 0, c_ = 1;
+        if (ell) sincospi(2.0 * box_node(2 * (e ? ap2 : ap1) + h, level, tb.z[t]), &s_, &c_);
+        if (e) {
+            sxb[h][t] = s_;
+            cxb[h][t] = c_;
+        } else {
+            sxa[h][t] = s_;
+            cxa[h][t] = c_;
+        }
     }
     __syncthreads();
     // prefactor kernel values of the inputs
@@ -594,41 +612,27 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
         }
     }
     __syncthreads();
-    // remodulation kernel values of output j into table slot sl
-    for (int j = 0; j < 4; ++j) {
+    // remodulation kernel values of the four outputs, all four at once
+    for (int it = tid; it < 4 * QQ; it += NT) {
+        const int j = it / QQ, i = it - j * QQ;
         const int j1 = j >> 1, j2 = j & 1;
         const int a1 = 2 * ap1 + j1, a2 = 2 * ap2 + j2;
-        if (tid < Q) {
-            double s_ = 0, c_ = 1;
-            if (ell) sincospi(2.0 * box_node(a1, level, tb.z[tid]), &s_, &c_);
-            sx1[tid] = s_;
-            cx1[tid] = c_;
-        } else if (tid >= 64 && tid < 64 + Q) {
-            const int t = tid - 64;
-            double s_ = 0, c_ = 1;
-            if (ell) sincospi(2.0 * box_node(a2, level, tb.z[t]), &s_, &c_);
-            sx2[t] = s_;
-            cx2[t] = c_;
-        }
-        __syncthreads();
-        for (int i = tid; i < QQ; i += NT) {
-            const int t1 = i / Q, t2 = i - t1 * Q;
-            const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[t2]), sx1[t1],
-                                     cx1[t1], sx2[t2], cx2[t2]);
-            const G3 G0 = phase_dir3(xp, ph, ct0[0], st0[0]);
-            const G3 G1 = phase_dir3(xp, ph, ct0[1], st0[1]);
+        const int t1 = i / Q, t2 = i - t1 * Q;
+        const XP xp = make_xp_sc(ph, box_node(a1, level, tb.z[t1]), box_node(a2, level, tb.z[t2]), sxa[j1][t1],
+                                 cxa[j1][t1], sxb[j2][t2], cxb[j2][t2]);
+        const G3 G0 = phase_dir3(xp, ph, ct0[0], st0[0]);
+        const G3 G1 = phase_dir3(xp, ph, ct0[1], st0[1]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int c1 = c >> 1, c2 = c & 1;
-                const G3 &G = c2 ? G1 : G0;
-                const double rho = r0c[c1];
-                Er[j][c][i] = cis<T>(rho * G.g);
-                Sr[0][j][c][i] = (T)(TWO_PI * (rho * G.d1));
-                Sr[1][j][c][i] = (T)(TWO_PI * (rho * G.d2));
-            }
+        for (int c = 0; c < 4; ++c) {
+            const int c1 = c >> 1, c2 = c & 1;
+            const G3 &G = c2 ? G1 : G0;
+            const double rho = r0c[c1];
+            Er[j][c][i] = cis<T>(rho * G.g);
+            Sr[0][j][c][i] = (T)(TWO_PI * (rho * G.d1));
+            Sr[1][j][c][i] = (T)(TWO_PI * (rho * G.d2));
         }
-        __syncthreads();
     }
+    __syncthreads();
     // the two contractions go row by row (a thread loads one row of its
     // operand into registers once, the interpolation matrix comes through
     // the scalar cache): pass 1, rows (k, c, t'1), outputs t2 in half (w & 1);
