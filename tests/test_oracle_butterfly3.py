@@ -80,3 +80,31 @@ def test_model3_planted_mistakes_are_caught(bad):
     wrong = _err(N, q, kind, 0, 1, f, model=bad)
     print(f"{bad.__name__}: {wrong:.3f} vs {good:.3f}")
     assert wrong > 0.5 and wrong > 3 * good
+
+
+def test_model3_fourier_rate_matches_the_2d_model():
+    """The 3-D model's error for the Fourier phase (the 3-D DFT) falls with q
+    at the rate of the 2-D model's at the same N and schedule (N = 16, s = 2,
+    lm = 2): about 0.75 / 0.32 in 3-D against 0.68 / 0.30 in 2-D at q = 3 / 5
+    (0.12 against 0.12 at q = 7, 30 s here and left out).  The 2-D model is
+    pinned to converge spectrally as q grows, so the 3-D errors of eq:ex3 at
+    q = 7 come from the same interpolation rate on the spherical boxes, not
+    from a step of the 3-D model."""
+    from oracle import direct as D
+    from oracle.butterfly import ButterflyModel
+    from workloads import white_noise
+
+    N = 16
+    f3 = _noise(N, 5)
+    ref3 = B.direct3(N, B.FOURIER, f3)
+    f2 = white_noise(N, 5)
+    ph2 = D.Phase(kind=D.FOURIER)
+    ref2 = D.forward(N, ph2, f2)
+    for q in (3, 5):
+        m3 = B.ButterflyModel3(N, q, B.FOURIER)
+        m2 = ButterflyModel(N, q, ph2)
+        assert (m3.s, m3.lm) == (m2.s, m2.lm) == (2, 2)
+        e3 = float(np.linalg.norm(m3.apply(f3).ravel() - ref3) / np.linalg.norm(ref3))
+        e2 = float(np.linalg.norm(m2.apply(f2).ravel() - ref2.ravel()) / np.linalg.norm(ref2))
+        print(f"q={q}: 3-D {e3:.3f}, 2-D {e2:.3f}")
+        assert 0.7 < e3 / e2 < 1.4
