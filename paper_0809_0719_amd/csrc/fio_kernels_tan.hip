@@ -170,6 +170,25 @@ __device__ __forceinline__ void fetch_planes(cpx<T> (&d)[3][NP], const cpx<T> *s
     }
 }
 
+// Outputs (children j) a tangent level kernel takes per pass: two where the
+// second set of pass buffers still fits the workgroup's LDS (160 KB), else
+// one.  Two halve the workgroup barriers per right-hand side and keep about
+// twice the threads busy in every pass.
+template <typename T, int Q>
+constexpr int plevel_tan_lds(int jp) {
+    constexpr int QQ = Q * Q, C = 2 * (int)sizeof(T), S = (int)sizeof(T);
+    return jp * 18 * QQ * C + 20 * QQ * C + 40 * QQ * S + 9 * Q * 8 + 12 * Q * 24;
+}
+template <typename T, int Q>
+constexpr int xlevel_tan_lds(int jp) {
+    constexpr int QQ = Q * Q, C = 2 * (int)sizeof(T), S = (int)sizeof(T);
+    return (12 + jp * 12) * QQ * C + 20 * QQ * C + 40 * QQ * S + 12 * Q * 8 + 6 * 8;
+}
+template <typename T, int Q>
+constexpr int plevel_tan_jp() { return plevel_tan_lds<T, Q>(2) <= 150 * 1024 ? 2 : 1; }
+template <typename T, int Q>
+constexpr int xlevel_tan_jp() { return xlevel_tan_lds<T, Q>(2) <= 150 * 1024 ? 2 : 1; }
+
 // ===========================================================================
 // p-recursion (eq:alg2b) with derivatives, one workgroup per block (A_p, B),
 // the four outputs one after another:
@@ -186,8 +205,9 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
                                                    size_t rstride) {
     constexpr int QQ = Q * Q;
     constexpr double TWO_PI = 6.283185307179586476925286766559;
-    __shared__ cpx<T> v[3][4 * QQ];
-    __shared__ cpx<T> W[3][2 * QQ];
+    constexpr int JP = plevel_tan_jp<T, Q>();
+    __shared__ cpx<T> v[JP][3][4 * QQ];
+    __shared__ cpx<T> W[JP][3][2 * QQ];
     __shared__ double rc[2 * Q], ctc[2 * Q], stc[2 * Q];
     __shared__ double rb[Q], ctb[Q], stb[Q];
     __shared__ G3 Gc[4][2 * Q], Gb[4][Q];
@@ -258,8 +278,9 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
     // the two contractions go row by row: a thread loads one row of its
     // operand into registers once and makes a run of outputs from it, with
     // the interpolation matrix read through the scalar cache (wave-uniform
-    // offsets).  Pass 1, rows (k, c1, t'1), outputs t2 in half (w & 1);
-    // pass 2, rows (k, t2), outputs t1 in quarter w.
+    // offsets).  JP outputs j = JP jp + jj per pass.  Pass 1, rows
+    // (jj, k, c1, t'1), outputs t2 in half (w & 1); pass 2, rows (jj, k, t2),
+    // outputs t1 in quarter w.
     constexpr int HA = (Q + 1) / 2, HB = (Q + 3) / 4, NPT = (4 * QQ + NT - 1) / NT;
     cptr<T> Mg = to_constant(pick_M<T>(tb));
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -269,33 +290,38 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
     fetch_planes<T, 4 * QQ>(xin, win + blk * (4 * QQ), plane, tid);
     for (int r = 0; r < nrhs; ++r) {
         fetch_planes<T, 4 * QQ>(xnx, win + (size_t)min(r + 1, nrhs - 1) * rstride + blk * (4 * QQ), plane, tid);
-        for (int j = 0; j < 4; ++j) {
+        for (int jp = 0; jp < 4 / JP; ++jp) {
             opaque_sgpr(Mg);
 #pragma unroll
             for (int n = 0; n < NPT; ++n) {
                 const int i = tid + n * NT;
                 if (i < 4 * QQ) {
-                    const cpx<T> e = Ep[j][i];
                     const cpx<T> in0 = xin[0][n];
-                    const T s1 = Sp[0][j][i], s2 = Sp[1][j][i];
-                    v[0][i] = cmul(e, in0);
-                    v[1][i] = cmul(e, cadd(xin[1][n], cpx<T>{-s1 * in0.im, s1 * in0.re}));
-                    v[2][i] = cmul(e, cadd(xin[2][n], cpx<T>{-s2 * in0.im, s2 * in0.re}));
+#pragma unroll
+                    for (int jj = 0; jj < JP; ++jj) {
+                        const int j = JP * jp + jj;
+                        const cpx<T> e = Ep[j][i];
+                        const T s1 = Sp[0][j][i], s2 = Sp[1][j][i];
+                        v[jj][0][i] = cmul(e, in0);
+                        v[jj][1][i] = cmul(e, cadd(xin[1][n], cpx<T>{-s1 * in0.im, s1 * in0.re}));
+                        v[jj][2][i] = cmul(e, cadd(xin[2][n], cpx<T>{-s2 * in0.im, s2 * in0.re}));
+                    }
                 }
             }
             __syncthreads();
             // W[k][c1][t'1][t2] = sum_{c2, t'2} M_c2[t2][t'2] v[k][2 c1 + c2][t'1][t'2]
             with_uniform<0, 2>(w & 1, [&](auto hc) {
                 constexpr int t0 = decltype(hc)::value * HA, nt = Q - t0 < HA ? Q - t0 : HA;
-                for (int row = (w >> 1) * 64 + lane; row < 6 * Q; row += 128) {
-                    const int k = row / (2 * Q), rem = row - k * 2 * Q;
+                for (int row = (w >> 1) * 64 + lane; row < JP * 6 * Q; row += 128) {
+                    const int jj = row / (6 * Q), rj = row - jj * 6 * Q;
+                    const int k = rj / (2 * Q), rem = rj - k * 2 * Q;
                     const int c1 = rem / Q, tp1 = rem - c1 * Q;
                     cpx<T> acc[nt];
 #pragma unroll
                     for (int u = 0; u < nt; ++u) acc[u] = {(T)0, (T)0};
 #pragma unroll
                     for (int c2 = 0; c2 < 2; ++c2) {
-                        const cpx<T> *vv = v[k] + (2 * c1 + c2) * QQ + tp1 * Q;
+                        const cpx<T> *vv = v[jj][k] + (2 * c1 + c2) * QQ + tp1 * Q;
 #pragma unroll
                         for (int tp2 = 0; tp2 < Q; ++tp2) {
                             const cpx<T> x = vv[tp2];
@@ -303,19 +329,20 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
                             for (int u = 0; u < nt; ++u) crfma(acc[u], Mg[c2 * QQ + (t0 + u) * Q + tp2], x);
                         }
                     }
-                    cpx<T> *ww = W[k] + c1 * QQ + tp1 * Q + t0;
+                    cpx<T> *ww = W[jj][k] + c1 * QQ + tp1 * Q + t0;
 #pragma unroll
                     for (int u = 0; u < nt; ++u) ww[u] = acc[u];
                 }
             });
             __syncthreads();
-            // o[k][t1][t2] = sum_{c1, t'1} M_c1[t1][t'1] W[k][c1][t'1][t2], into v[k][0, QQ)
+            // o[k][t1][t2] = sum_{c1, t'1} M_c1[t1][t'1] W[k][c1][t'1][t2], into v[jj][k][0, QQ)
             with_uniform<0, 4>(w, [&](auto pc) {
                 constexpr int t0 = decltype(pc)::value * HB;
                 constexpr int nt = Q - t0 >= HB ? HB : (Q - t0 > 0 ? Q - t0 : 0);
                 if constexpr (nt > 0) {
-                    if (lane < 3 * Q) {
-                        const int k = lane / Q, t2 = lane - k * Q;
+                    for (int row = lane; row < JP * 3 * Q; row += 64) {
+                        const int jj = row / (3 * Q), rj = row - jj * 3 * Q;
+                        const int k = rj / Q, t2 = rj - k * Q;
                         cpx<T> acc[nt];
 #pragma unroll
                         for (int u = 0; u < nt; ++u) acc[u] = {(T)0, (T)0};
@@ -323,25 +350,27 @@ __global__ __launch_bounds__(NT) void k_plevel_tan(Geom g, PhaseDev ph, Tables t
                         for (int c1 = 0; c1 < 2; ++c1) {
 #pragma unroll
                             for (int tp1 = 0; tp1 < Q; ++tp1) {
-                                const cpx<T> x = W[k][c1 * QQ + tp1 * Q + t2];
+                                const cpx<T> x = W[jj][k][c1 * QQ + tp1 * Q + t2];
 #pragma unroll
                                 for (int u = 0; u < nt; ++u) crfma(acc[u], Mg[c1 * QQ + (t0 + u) * Q + tp1], x);
                             }
                         }
 #pragma unroll
-                        for (int u = 0; u < nt; ++u) v[k][(t0 + u) * Q + t2] = acc[u];
+                        for (int u = 0; u < nt; ++u) v[jj][k][(t0 + u) * Q + t2] = acc[u];
                     }
                 }
             });
             __syncthreads();
-            cpx<T> *dst = wout + r * rstride + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
-            for (int i = tid; i < QQ; i += NT) {
+            for (int it = tid; it < JP * QQ; it += NT) {
+                const int jj = it / QQ, i = it - jj * QQ;
+                const int j = JP * jp + jj;
+                cpx<T> *dst = wout + r * rstride + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
                 const cpx<T> e = Er[j][i];
-                const cpx<T> o0 = cmulc(v[0][i], e);
+                const cpx<T> o0 = cmulc(v[jj][0][i], e);
                 const T s1 = Sr[0][j][i], s2 = Sr[1][j][i];
                 dst[i] = o0;
-                dst[plane + i] = csub(cmulc(v[1][i], e), cpx<T>{-s1 * o0.im, s1 * o0.re});
-                dst[2 * plane + i] = csub(cmulc(v[2][i], e), cpx<T>{-s2 * o0.im, s2 * o0.re});
+                dst[plane + i] = csub(cmulc(v[jj][1][i], e), cpx<T>{-s1 * o0.im, s1 * o0.re});
+                dst[2 * plane + i] = csub(cmulc(v[jj][2][i], e), cpx<T>{-s2 * o0.im, s2 * o0.re});
             }
             __syncthreads();
         }
@@ -542,8 +571,9 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
                                                    size_t rstride) {
     constexpr int QQ = Q * Q;
     constexpr double TWO_PI = 6.283185307179586476925286766559;
+    constexpr int JP = xlevel_tan_jp<T, Q>();
     __shared__ cpx<T> v[3][4 * QQ];
-    __shared__ cpx<T> Y[3][4 * QQ];
+    __shared__ cpx<T> Y[JP][3][4 * QQ];
     __shared__ double sx1[Q], cx1[Q], sx2[Q], cx2[Q];
     __shared__ double sxa[2][Q], cxa[2][Q], sxb[2][Q], cxb[2][Q];  // nodes of the children's boxes
     __shared__ double r0c[2], ct0[2], st0[2];
@@ -635,8 +665,8 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
     __syncthreads();
     // the two contractions go row by row (a thread loads one row of its
     // operand into registers once, the interpolation matrix comes through
-    // the scalar cache): pass 1, rows (k, c, t'1), outputs t2 in half (w & 1);
-    // pass 2 in place, one thread per column (k, c, t2), all t1.
+    // the scalar cache), JP outputs j = JP jp + jj per pass: pass 1, rows
+    // (k, c, t'1); pass 2 in place, one thread per column (jj, k, c, t2), all t1.
     constexpr int HA = (Q + 1) / 2, NPT = (4 * QQ + NT - 1) / NT;
     cptr<T> Mg = to_constant(pick_M<T>(tb));
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -658,36 +688,44 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
             }
         }
         __syncthreads();
-        for (int j = 0; j < 4; ++j) {
-            const int j1 = j >> 1, j2 = j & 1;
+        for (int jp = 0; jp < 4 / JP; ++jp) {
+            const int j1 = (JP * jp) >> 1;  // the same for the JP outputs of this pass
             opaque_sgpr(Mg);
-            // Y[k][c][t'1][t2] = sum_{t'2} M_j2[t'2][t2] v[k][c][t'1][t'2]
-            with_uniform<0, 2>(w & 1, [&](auto hc) {
-                constexpr int t0 = decltype(hc)::value * HA, nt = Q - t0 < HA ? Q - t0 : HA;
-                for (int row = (w >> 1) * 64 + lane; row < 12 * Q; row += 128) {
-                    const int k = row / (4 * Q), rem = row - k * 4 * Q;
-                    const int c = rem / Q, tp1 = rem - c * Q;
-                    const cpx<T> *vv = v[k] + c * QQ + tp1 * Q;
-                    cpx<T> acc[nt];
+            // Y[jj][k][c][t'1][t2] = sum_{t'2} M_j2[t'2][t2] v[k][c][t'1][t'2], j2 = (JP jp + jj) & 1.
+            // JP = 2: jj = w >> 1 (wave-uniform j2), every t2; JP = 1: t2 in half (w & 1)
+            with_uniform<0, 2>(JP == 2 ? 0 : (w & 1), [&](auto hc) {
+                constexpr int HO = JP == 2 ? Q : HA;
+                constexpr int t0 = decltype(hc)::value * HO, nt = Q - t0 < HO ? Q - t0 : HO;
+                const int jj = JP == 2 ? (w >> 1) : 0;
+                const int j2 = (JP * jp + jj) & 1;
+                const int rg = JP == 2 ? (w & 1) : (w >> 1);
+                if constexpr (nt > 0) {
+                    for (int row = rg * 64 + lane; row < 12 * Q; row += 128) {
+                        const int k = row / (4 * Q), rem = row - k * 4 * Q;
+                        const int c = rem / Q, tp1 = rem - c * Q;
+                        const cpx<T> *vv = v[k] + c * QQ + tp1 * Q;
+                        cpx<T> acc[nt];
 #pragma unroll
-                    for (int u = 0; u < nt; ++u) acc[u] = {(T)0, (T)0};
+                        for (int u = 0; u < nt; ++u) acc[u] = {(T)0, (T)0};
 #pragma unroll
-                    for (int tp2 = 0; tp2 < Q; ++tp2) {
-                        const cpx<T> x = vv[tp2];
+                        for (int tp2 = 0; tp2 < Q; ++tp2) {
+                            const cpx<T> x = vv[tp2];
 #pragma unroll
-                        for (int u = 0; u < nt; ++u) crfma(acc[u], Mg[j2 * QQ + tp2 * Q + t0 + u], x);
+                            for (int u = 0; u < nt; ++u) crfma(acc[u], Mg[j2 * QQ + tp2 * Q + t0 + u], x);
+                        }
+                        cpx<T> *yy = Y[jj][k] + c * QQ + tp1 * Q + t0;
+#pragma unroll
+                        for (int u = 0; u < nt; ++u) yy[u] = acc[u];
                     }
-                    cpx<T> *yy = Y[k] + c * QQ + tp1 * Q + t0;
-#pragma unroll
-                    for (int u = 0; u < nt; ++u) yy[u] = acc[u];
                 }
             });
             __syncthreads();
             // z[k][c][t1][t2] = sum_{t'1} M_j1[t'1][t1] Y[k][c][t'1][t2], in place
-            for (int row = tid; row < 12 * Q; row += NT) {
-                const int k = row / (4 * Q), rem = row - k * 4 * Q;
+            for (int row = tid; row < JP * 12 * Q; row += NT) {
+                const int jj = row / (12 * Q), rj = row - jj * 12 * Q;
+                const int k = rj / (4 * Q), rem = rj - k * 4 * Q;
                 const int c = rem / Q, t2 = rem - c * Q;
-                cpx<T> *yy = Y[k] + c * QQ + t2;
+                cpx<T> *yy = Y[jj][k] + c * QQ + t2;
                 cpx<T> x[Q];
 #pragma unroll
                 for (int tp1 = 0; tp1 < Q; ++tp1) x[tp1] = yy[tp1 * Q];
@@ -702,12 +740,14 @@ __global__ __launch_bounds__(NT) void k_xlevel_tan(Geom g, PhaseDev ph, Tables t
                 }
             }
             __syncthreads();
-            cpx<T> *dst = wout + r * rstride + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
-            for (int i = tid; i < QQ; i += NT) {
+            for (int it = tid; it < JP * QQ; it += NT) {
+                const int jj = it / QQ, i = it - jj * QQ;
+                const int j = JP * jp + jj;
+                cpx<T> *dst = wout + r * rstride + ((size_t)(4 * mAp + j) * nBl + mB) * QQ;
                 cpx<T> out[3] = {{(T)0, (T)0}, {(T)0, (T)0}, {(T)0, (T)0}};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const cpx<T> z0 = Y[0][c * QQ + i], z1 = Y[1][c * QQ + i], z2 = Y[2][c * QQ + i];
+                    const cpx<T> z0 = Y[jj][0][c * QQ + i], z1 = Y[jj][1][c * QQ + i], z2 = Y[jj][2][c * QQ + i];
                     const cpx<T> e = Er[j][c][i];
                     const T s1 = Sr[0][j][c][i], s2 = Sr[1][j][c][i];
                     cfma(out[0], e, z0);
