@@ -170,10 +170,11 @@ __device__ __forceinline__ void fetch_planes(cpx<T> (&d)[3][NP], const cpx<T> *s
     }
 }
 
-// Outputs (children j) a tangent level kernel takes per pass: two where the
-// second set of pass buffers still fits the workgroup's LDS (160 KB), else
-// one.  Two halve the workgroup barriers per right-hand side and keep about
-// twice the threads busy in every pass.
+// Outputs (children j) a tangent level kernel takes per pass: two while two
+// workgroups still share a CU's 160 KB of LDS, else one.  Two halve the
+// workgroup barriers per right-hand side and keep about twice the threads
+// busy in every pass (at q = 9, FP32: 52 KB, three workgroups per CU, a third
+// less time than one output per pass at four).
 template <typename T, int Q>
 constexpr int plevel_tan_lds(int jp) {
     constexpr int QQ = Q * Q, C = 2 * (int)sizeof(T), S = (int)sizeof(T);
@@ -185,9 +186,9 @@ constexpr int xlevel_tan_lds(int jp) {
     return (12 + jp * 12) * QQ * C + 20 * QQ * C + 40 * QQ * S + 12 * Q * 8 + 6 * 8;
 }
 template <typename T, int Q>
-constexpr int plevel_tan_jp() { return plevel_tan_lds<T, Q>(2) <= 150 * 1024 ? 2 : 1; }
+constexpr int plevel_tan_jp() { return plevel_tan_lds<T, Q>(2) <= 80 * 1024 ? 2 : 1; }
 template <typename T, int Q>
-constexpr int xlevel_tan_jp() { return xlevel_tan_lds<T, Q>(2) <= 150 * 1024 ? 2 : 1; }
+constexpr int xlevel_tan_jp() { return xlevel_tan_lds<T, Q>(2) <= 80 * 1024 ? 2 : 1; }
 
 // ===========================================================================
 // p-recursion (eq:alg2b) with derivatives, one workgroup per block (A_p, B),
