@@ -241,3 +241,29 @@ def test_phase_gradient_descent_recovers_velocity_scaling():
     assert all(b < a_ for a_, b in zip(losses, losses[1:]))
     assert losses[-1] < 1e-3 * losses[0]
     assert np.abs(a.detach().numpy() - 1.0).max() < 1e-4
+
+
+def test_dphase_at_the_benchmark_size():
+    """The benchmark's configuration: N = 1024, q = 9, eq:ex1, complex64, a
+    plan of nrhs_max = 64 and 64 right-hand sides (chunks of 16 through the
+    paired level kernels and the register-table switch).  Properties that hold
+    at any size: the primal plane equals fio_apply's batched forward to FP32
+    rounding for every right-hand side, and the first and last right-hand
+    sides equal the single-right-hand-side pass bit for bit (which the small
+    cases above pin to the oracle's difference quotients)."""
+    N, q, R = 1024, 9, 64
+    ph = D.Phase()
+    plan = _plan(N, q, ph, None, None, torch.complex64, nrhs_max=R)
+    f = _dev(white_noise(N, 31, nrhs=R), torch.complex64)
+    u, d1, d2 = plan.apply_dphase(f)
+    ua = plan.apply(f)
+    err = max(rel_max(u[r].cpu().numpy(), ua[r].cpu().numpy()) for r in (0, 17, 40, 63))
+    print(f"dphase N=1024 q=9 64 RHS: primal vs fio_apply {err:.2e}")
+    # two FP32 paths (dense passes here, symmetric passes and matrix cores
+    # there), each within 8e-5 relative max of the FP64 model
+    assert err <= 1.6e-4
+    for r in (0, R - 1):
+        u1, c1, c2 = plan.apply_dphase(f[r])
+        assert torch.equal(u1, u[r]) and torch.equal(c1, d1[r]) and torch.equal(c2, d2[r]), r
+    assert torch.isfinite(d1).all() and torch.isfinite(d2).all()
+    assert torch.count_nonzero(d1).item() > 0.99 * d1.numel()
