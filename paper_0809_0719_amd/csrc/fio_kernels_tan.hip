@@ -54,7 +54,16 @@ __device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) {
     return {a.re - b.re, a.im - b.im};
 }
 
-constexpr int SCT = 16;  // sources per chunk in the tangent initialisation
+// Sources per chunk in the tangent initialisation: 64 (a whole box B at
+// s = 3, on average) where the chunk's products for all ACH boxes A fit in
+// 48 KB of LDS, else 32 or 16.  A chunk costs one pass of Lagrange rows and
+// three workgroup barriers.
+template <typename T, int Q>
+constexpr int init_tan_sct() {
+    constexpr int ACH = (NT / Q) < 64 ? (NT / Q) : 64;
+    constexpr int per = 3 * ACH * 2 * (int)sizeof(T);
+    return 64 * per <= 48 * 1024 ? 64 : 32 * per <= 48 * 1024 ? 32 : 16;
+}
 
 // ===========================================================================
 // initialisation (eq:alg2a) with derivatives:
@@ -66,6 +75,7 @@ __global__ __launch_bounds__(NT) void k_init_tan(Geom g, PhaseDev ph, Tables tb,
                                                  const cpx<T> *__restrict__ f, cpx<T> *__restrict__ w,
                                                  size_t plane) {
     constexpr int ACH = (NT / Q) < 64 ? (NT / Q) : 64;
+    constexpr int SCT = init_tan_sct<T, Q>();
     __shared__ T lag1[SCT][Q];
     __shared__ T lag2[SCT][Q];
     __shared__ cpx<T> gA[3][ACH][SCT];
@@ -106,14 +116,17 @@ __global__ __launch_bounds__(NT) void k_init_tan(Geom g, PhaseDev ph, Tables tb,
     __syncthreads();
     for (int c0 = beg; c0 < end; c0 += SCT) {
         const int n = min(SCT, end - c0);
+        // the two Lagrange rows of a source on two threads (SCT <= 64 < NT / 2)
         if (tid < n) {
             const int j = c0 + tid;
             const int idx = src.idx[j];
             const double2 p = src.p[j];
             lagrange_row<T, Q>(p.x * scale - ((double)bp1 + 0.5), zs, ls, lag1[tid]);
-            lagrange_row<T, Q>(p.y * scale - ((double)bp2 + 0.5), zs, ls, lag2[tid]);
             kk[tid] = make_double2((double)(idx / g.N - g.N / 2), (double)(idx % g.N - g.N / 2));
             fs[tid] = f[idx];
+        } else if (tid >= 64 && tid < 64 + n) {
+            const double2 p = src.p[c0 + tid - 64];
+            lagrange_row<T, Q>(p.y * scale - ((double)bp2 + 0.5), zs, ls, lag2[tid - 64]);
         }
         __syncthreads();
         for (int it = tid; it < nAc * n; it += NT) {
