@@ -141,12 +141,14 @@ def test_dphase_several_rhs_and_workspace_reuse(dtype):
 
 
 @pytest.mark.parametrize("dtype,N,q,s", [(torch.complex64, 64, 9, 1), (torch.complex128, 64, 9, 1),
-                                          (torch.complex64, 32, 12, 1), (torch.complex128, 32, 12, 1)])
+                                          (torch.complex64, 32, 12, 1), (torch.complex128, 32, 12, 1),
+                                          (torch.complex64, 32, 5, 1), (torch.complex64, 32, 6, 1)])
 def test_dphase_batched_levels_equal_one_at_a_time(dtype, N, q, s):
     """A plan with nrhs_max = 9 takes the tangent in chunks of three right-hand
     sides (three weight planes each); seven of them (chunks 3, 3, 1) through
-    the batched level kernels give bit for bit what one at a time gives, with
-    two p-levels and two x-levels on the path."""
+    the batched level and switch kernels give bit for bit what one at a time
+    gives, with two p-levels and two x-levels on the path; odd and even q
+    (the switch's middle node row, the levels' paired passes)."""
     ph = D.Phase(a1=1.1, a2=0.85, eta1=0.2)
     f = _dev(white_noise(N, 21, nrhs=7), dtype)
     p9 = _plan(N, q, ph, s, None, dtype, nrhs_max=9)
