@@ -42,6 +42,7 @@ METRIC_TOL = 1e-4
 # does not use)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak (no sparsity)
 CSIZE = 8  # bytes of one complex64 value
 
 
@@ -84,19 +85,23 @@ def algorithmic_work(kind: str, N: int, q: int, s: int, nrhs: int):
 def roofline_of(kind: str, avg_ms: float, launches: int, N: int, q: int, s: int, nrhs: int,
                 contract: str = "fp") -> dict:
     """Both bounds of one kernel kind: achieved GB/s against the HBM peak and
-    achieved TFLOP/s against the FP32 peak; the binding one is the larger
-    fraction (the bound the kernel is closest to)."""
+    achieved TFLOP/s against the peak of the arithmetic it runs on (FP32, or
+    BF16 matrix cores for the p-level under contract "bf16"); the binding one
+    is the larger fraction (the bound the kernel is closest to)."""
     nbytes, flops = algorithmic_work(kind, N, q, s, nrhs)
     sec = avg_ms * 1e-3
     gbs, tfs = nbytes / sec / 1e9, flops / sec / 1e12
-    hf, ff = gbs / HBM_PEAK_GBS, tfs / FP32_PEAK_TFLOPS
+    peak = BF16_PEAK_TFLOPS if (contract == "bf16" and kind == "plevel") else FP32_PEAK_TFLOPS
+    hf, ff = gbs / HBM_PEAK_GBS, tfs / peak
     out = {"avg_ms": avg_ms, "launches": launches, "nrhs": nrhs, "bytes": nbytes, "flops": flops,
            "hbm_gbs": gbs, "hbm_frac": hf, "fp32_tflops": tfs, "fp32_frac": ff,
-           "bound_ms": max(nbytes / (HBM_PEAK_GBS * 1e9), flops / (FP32_PEAK_TFLOPS * 1e12)) * 1e3}
+           "bound_ms": max(nbytes / (HBM_PEAK_GBS * 1e9), flops / (peak * 1e12)) * 1e3}
+    if peak != FP32_PEAK_TFLOPS:
+        out.update(compute_peak_tflops=peak)
     if hf >= ff:
         out.update(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hf)
     else:
-        out.update(bound="mfma" if kind in mfma_kinds(q, s, nrhs, contract) else "alu", achieved=tfs, peak=FP32_PEAK_TFLOPS,
+        out.update(bound="mfma" if kind in mfma_kinds(q, s, nrhs, contract) else "alu", achieved=tfs, peak=peak,
                    unit="TFLOP/s", frac=ff)
     return out
 
@@ -105,7 +110,8 @@ def mfma_kinds(q: int, s: int, nrhs: int, contract: str = "fp") -> tuple:
     """Kernel kinds the library runs as FP32 matrix-core products for a
     complex64 plan: the initialisations at s = 3, q <= 9; the switches for
     chunks of 32 or more right-hand sides at q <= 9; with contract "mfma" also
-    the p-levels and adjoint x-levels of such chunks."""
+    the p-levels and adjoint x-levels of such chunks; with contract "bf16" the
+    p-levels (BF16 matrix cores, any number of right-hand sides)."""
     kinds = []
     if s == 3 and 3 <= q <= 9:
         kinds += ["init", "init_adj"]
@@ -113,6 +119,8 @@ def mfma_kinds(q: int, s: int, nrhs: int, contract: str = "fp") -> tuple:
         kinds += ["switch", "switch_adj"]
         if contract == "mfma":
             kinds += ["plevel", "xlevel_adj"]
+    if contract == "bf16":
+        kinds += ["plevel"]
     return tuple(kinds)
 
 

@@ -32,3 +32,11 @@ def test_kernel_pricing_follows_the_dispatch_rule():
     assert flops == 4.0 * 9 ** 4 * 1024 ** 2 and nbytes == 2 * 1024 ** 2 * 81 * 8
     r = bench.roofline_of("switch", 1.0, 1, 1024, 9, 3, 64)
     assert r["bound"] in ("hbm", "mfma") and abs(r["frac"] - max(r["hbm_frac"], r["fp32_frac"])) < 1e-12
+    # the BF16 p-level is priced against the BF16 matrix-core peak, the other kinds against FP32
+    assert "plevel" in bench.mfma_kinds(7, 3, 64, "bf16") and "xlevel" not in bench.mfma_kinds(7, 3, 64, "bf16")
+    rb = bench.roofline_of("plevel", 1e-3, 1, 512, 7, 3, 64, "bf16")
+    rf = bench.roofline_of("plevel", 1e-3, 1, 512, 7, 3, 64, "fp")
+    assert rb["compute_peak_tflops"] == bench.BF16_PEAK_TFLOPS and "compute_peak_tflops" not in rf
+    if rb["bound"] != "hbm":
+        assert rb["bound"] == "mfma" and rb["peak"] == bench.BF16_PEAK_TFLOPS
+    assert abs(rb["fp32_frac"] * bench.BF16_PEAK_TFLOPS - rf["fp32_frac"] * bench.FP32_PEAK_TFLOPS) < 1e-6
