@@ -46,7 +46,7 @@ __device__ __forceinline__ bf16x8 mcat_operand(const float *Mg, int lane) {
 // second pass per column t2:           D[r][t1] = sum_k' W[r][k'] Bk[k'][t1],
 //   W[r][k'] = C_{k'}[r][t2]; then conj E(x0(A_j), p^B_t) and store.
 // ===========================================================================
-template <int Q>
+template <int Q, bool STG>
 __global__ __launch_bounds__(256) void k_plevel_mfma(Geom g, PhaseDev ph, Tables tb, int level,
                                                     const cpx<float> *__restrict__ win,
                                                     cpx<float> *__restrict__ wout, int nrhs, size_t plane) {
@@ -58,6 +58,15 @@ __global__ __launch_bounds__(256) void k_plevel_mfma(Geom g, PhaseDev ph, Tables
     __shared__ cpx<float> Epre[4][4 * QQ];           // per output: E(x0(A_j), p^{B_c}_t') [c][t'1][t'2]
     __shared__ cpx<float> Erem[4][QQ];               // per output: E(x0(A_j), p^B_t)
     __shared__ __bf16 Wre[4][Q][RT][KP], Wim[4][Q][RT][KP];   // per output: first-pass rows [t2][r][k']
+    // the block's inputs for one tile of right-hand sides, staged by coalesced
+    // loads and read by all four waves (row r padded by one value: the 16
+    // lanes that read one offset of 16 rows fall on different banks).  For
+    // q > 7 the buffer would leave one workgroup per CU (measured slower at
+    // q = 9), and a tile of fewer than RT / 2 right-hand sides gains nothing
+    // from it: there each lane loads its own right-hand side's inputs from
+    // global memory
+    constexpr bool STAGE = STG && Q <= 7;  // STG: the launch has RT / 2 or more right-hand sides
+    __shared__ cpx<float> xs[STAGE ? RT : 1][STAGE ? 4 * QQ + 1 : 1];
 
     const int tid = threadIdx.x;
     const int j = tid >> 6, lane = tid & 63;
@@ -118,10 +127,22 @@ __global__ __launch_bounds__(256) void k_plevel_mfma(Geom g, PhaseDev ph, Tables
     __syncthreads();
 
     for (int r0 = 0; r0 < nrhs; r0 += RT) {
+        // stage the tile's inputs (4 q^2 consecutive values per right-hand
+        // side; zero past nrhs); the previous tile's readers finished at the
+        // barrier that closed it
+        const bool staged = STAGE && nrhs - r0 >= RT / 2;  // uniform
+        if (staged) {
+            for (int i = tid; i < RT * 4 * QQ; i += 256) {
+                const int r = i / (4 * QQ), o = i - r * (4 * QQ);
+                xs[STAGE ? r : 0][STAGE ? o : 0] =
+                    r0 + r < nrhs ? win[(size_t)(r0 + r) * plane + blk * 4 * QQ + o] : cpx<float>{0.f, 0.f};
+            }
+            __syncthreads();
+        }
         // ---- first pass: rows k' = (c1, t'1); lane holds r = r0 + ln, k = 8 lg + e
         const int rA = r0 + ln;
-        const bool rok = rA < nrhs;
-        const cpx<float> *src = win + (size_t)rA * plane + blk * 4 * QQ;
+        const bool rok = staged || rA < nrhs;  // staged rows past nrhs are zero
+        const cpx<float> *src = staged ? &xs[STAGE ? ln : 0][0] : win + (size_t)min(rA, nrhs - 1) * plane + blk * 4 * QQ;
 #pragma unroll 1
         for (int kr = 0; kr < 2 * Q; ++kr) {
             const int c1 = kr / Q, tp1 = kr - c1 * Q;
@@ -188,8 +209,14 @@ template <int Q>
 static hipError_t plevel_mfma_q(const Geom &g, const PhaseDev &ph, const Tables &tb, int level, const void *win,
                                 void *wout, int nrhs, size_t plane, hipStream_t st) {
     const unsigned nblk = 1u << (2 * g.L - 2);
-    hipLaunchKernelGGL((k_plevel_mfma<Q>), dim3(nblk), dim3(256), 0, st, g, ph, tb, level,
-                       (const cpx<float> *)win, (cpx<float> *)wout, nrhs, plane);
+    // the staging buffer only where a tile can use it (its LDS would lower
+    // the occupancy of a launch of a few right-hand sides for nothing)
+    if (nrhs >= RT / 2)
+        hipLaunchKernelGGL((k_plevel_mfma<Q, true>), dim3(nblk), dim3(256), 0, st, g, ph, tb, level,
+                           (const cpx<float> *)win, (cpx<float> *)wout, nrhs, plane);
+    else
+        hipLaunchKernelGGL((k_plevel_mfma<Q, false>), dim3(nblk), dim3(256), 0, st, g, ph, tb, level,
+                           (const cpx<float> *)win, (cpx<float> *)wout, nrhs, plane);
     return hipGetLastError();
 }
 
